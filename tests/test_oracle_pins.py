@@ -1,0 +1,475 @@
+"""Pins of the CPU oracle against what the theory fixes (no GPU).
+
+Each test ties one part of the oracle to a closed form, an exact invariant, a
+textbook special case or a brute-force computation that does not reuse the
+piece under test.
+"""
+
+import math
+
+import mpmath
+import numpy as np
+import pytest
+import scipy.integrate as si
+import scipy.linalg as sla
+
+import workloads as w
+from oracle import bath, heom, hierarchy
+from oracle import model as om
+
+
+# ---------------------------------------------------------------- bath ------
+
+def test_pade_k1_by_hand():
+    # [0/1] Pade of F(z) = 1/6 - z/360 + ...: (1/6)/(1 + z/60) = 10/(z + 60),
+    # so 4 eta = 10 and xi^2 = 60.
+    xi, eta = bath.pade_poles(1)
+    assert xi[0] == pytest.approx(math.sqrt(60.0), rel=1e-14)
+    assert eta[0] == pytest.approx(2.5, rel=1e-14)
+
+
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_pade_order_of_contact(K):
+    # coth(x/2) - approx = O(x^(4K+1)) as x -> 0 because the Pade approximant
+    # matches 2K Taylor coefficients of F(z), z = x^2.  Measured against
+    # high-precision coth, halving x must shrink the error by 2^(4K+1).
+    xi, eta = bath.pade_poles(K, high_precision=True)
+    mpmath.mp.dps = 60
+
+    def err(x):
+        x = mpmath.mpf(x)
+        approx = 2 / x + sum(4 * e * x / (x * x + s ** 2) for s, e in zip(xi, eta))
+        return abs(mpmath.coth(x / 2) - approx)
+
+    ratio = float(err(0.4) / err(0.2))
+    assert ratio == pytest.approx(2.0 ** (4 * K + 1), rel=0.05)
+
+
+def test_pade_accuracy_and_matsubara_limit():
+    x = np.linspace(0.05, 10.0, 400)
+    exact = 1.0 / np.tanh(x / 2)
+    e2 = np.max(np.abs(bath.coth_approx(x, *bath.pade_poles(2)) - exact))
+    e4 = np.max(np.abs(bath.coth_approx(x, *bath.pade_poles(4)) - exact))
+    assert 1e-3 < e2 < 1e-2
+    assert e4 < 1e-6
+    # many Pade poles: the lowest ones approach the Matsubara frequencies 2 pi k
+    xi, eta = bath.pade_poles(16)
+    np.testing.assert_allclose(xi[:3], 2 * np.pi * np.arange(1, 4), rtol=1e-9)
+    np.testing.assert_allclose(eta[:3], 1.0, rtol=1e-9)
+    # Matsubara sum converges to coth slowly (error ~ 1/K)
+    xm, em = bath.matsubara_poles(4000)
+    assert abs(bath.coth_approx(np.array([3.0]), xm, em)[0] - 1 / np.tanh(1.5)) < 1e-3
+
+
+def test_bath_correlation_matches_fdt_integral():
+    # C(t) = int_0^inf J(w) [coth(beta w / 2) cos(wt) - i sin(wt)] dw with the
+    # Drude density J = (zeta/pi) gamma^2 w/(w^2 + gamma^2), the normalisation
+    # for which int J/w dw = zeta gamma / 2 = Lambda (Eqs. SDF, counter4,
+    # counterterm).  The exponential terms must reproduce it for t > 0; the
+    # [K-1/K] decomposition drops only a part concentrated at short times.
+    zeta, gamma, beta = 0.1, 0.2, 10.0
+
+    def J(x):
+        return zeta / np.pi * gamma ** 2 * x / (x * x + gamma ** 2)
+
+    def J_coth(x):
+        g = 2.0 / beta if x == 0 else x / np.tanh(beta * x / 2)
+        return zeta / np.pi * gamma ** 2 / (x * x + gamma ** 2) * g
+
+    lam = si.quad(lambda x: zeta / np.pi * gamma ** 2 / (x * x + gamma ** 2), 0, np.inf)[0]
+    assert lam == pytest.approx(zeta * gamma / 2, rel=1e-10)
+
+    def err(K, t):
+        nu, c = bath.drude_terms(zeta, gamma, beta, K, "pade")
+        re = si.quad(J_coth, 0, np.inf, weight="cos", wvar=t, limlst=200)[0]
+        # -int J sin(wt) dw has the closed form -(zeta gamma^2/2) exp(-gamma t)
+        im = -si.quad(J, 0, np.inf, weight="sin", wvar=t, limlst=200)[0]
+        C = np.sum(c * np.exp(-nu * t))
+        assert abs(im + zeta * gamma ** 2 / 2 * np.exp(-gamma * t)) < 1e-7 * abs(c[0])
+        assert abs(C.imag + zeta * gamma ** 2 / 2 * np.exp(-gamma * t)) < 1e-15
+        return abs(C.real - re) / abs(c[0])
+
+    for t in (1.0, 2.0, 5.0, 9.0):
+        assert err(12, t) < 1e-7
+    assert err(2, 5.0) < 1e-4 and err(2, 9.0) < 1e-4
+    assert err(2, 2.0) > err(4, 2.0) > err(12, 2.0)
+
+
+def test_bath_singular_gamma_rejected():
+    xi, _ = bath.pade_poles(2)
+    with pytest.raises(ValueError):
+        bath.drude_terms(0.1, xi[0] / 10.0, 10.0, 2, "pade")
+
+
+# ----------------------------------------------------------- hierarchy ------
+
+@pytest.mark.parametrize("M,L,N,NL", [(3, 4, 35, 15), (6, 5, 462, 252), (9, 6, 5005, 3003)])
+def test_hierarchy_counts(M, L, N, NL):
+    h = hierarchy.Hierarchy(M, L)
+    assert len(h) == N == math.comb(M + L, L)
+    assert int(np.sum(h.n.sum(1) == L)) == NL
+    # neighbour maps are mutually inverse
+    for j in range(M):
+        has = h.down[:, j] >= 0
+        assert np.all(h.up[h.down[has, j], j] == np.nonzero(has)[0])
+    # ordered by depth, unique
+    assert np.all(np.diff(h.n.sum(1)) >= 0)
+    assert len(set(map(tuple, h.n))) == N
+
+
+def test_hierarchy_brute_force_small():
+    h = hierarchy.Hierarchy(3, 3)
+    brute = {n for n in np.ndindex(4, 4, 4) if sum(n) <= 3}
+    assert set(map(tuple, h.n.tolist())) == brute
+
+
+# -------------------------------------------------------- single mode -------
+
+def test_harmonic_mode_ladder():
+    mode = dict(omega=1.3, g3=0.0, g4=0.0, V1=1.0, V2=0.0, zeta=0.0, gamma=0.2,
+                mu1=1.0, mu2=0.0, n_basis=12, n_keep=6, K=1)
+    m = om.single_mode(mode)
+    np.testing.assert_allclose(m.E, 1.3 * (np.arange(6) + 0.5), atol=1e-12)
+    Q1 = np.diag(np.sqrt(np.arange(1, 6) / 2.0), 1)
+    np.testing.assert_allclose(np.abs(m.Q1), np.abs(Q1 + Q1.T), atol=1e-12)
+    # q^2 is built before truncation: <5|q^2|5> = 5.5, not (Q1 Q1)[5,5] = 2.5
+    assert m.Q2[5, 5] == pytest.approx(5.5, abs=1e-12)
+
+
+def test_anharmonic_levels_perturbation_theory():
+    # E_n = (n+1/2) + (g4/32)(2n^2+2n+1) - (g3^2/288)(30n^2+30n+11) + O(g^3)
+    g3, g4 = -0.02, 0.01
+    mode = dict(omega=1.0, g3=g3, g4=g4, V1=1.0, V2=0.0, zeta=0.0, gamma=0.2,
+                mu1=1.0, mu2=0.0, n_basis=40, n_keep=6, K=1)
+    m = om.single_mode(mode)
+    n = np.arange(6)
+    pt = (n + 0.5) + g4 / 32 * (2 * n * n + 2 * n + 1) - g3 * g3 / 288 * (30 * n * n + 30 * n + 11)
+    assert np.max(np.abs(m.E - pt)) < 1e-4
+
+
+def test_operators_symmetric_and_counter_term():
+    p, _ = w.cfg3(depth=1)
+    m = om.build(p)
+    for A in [m.H, m.mu] + m.V:
+        np.testing.assert_allclose(A, A.T, atol=1e-13)
+    np.testing.assert_allclose(m.mu_plus + m.mu_minus + np.where(
+        om.quanta(m.dims)[:, None] == om.quanta(m.dims)[None, :], m.mu, 0.0), m.mu, atol=0)
+    # harmonic mode with V = q: H_S' = H_A + Lambda q^2 exactly in the kept basis
+    mode = dict(omega=1.0, g3=0.0, g4=0.0, V1=1.0, V2=0.0, zeta=0.1, gamma=0.2,
+                mu1=1.0, mu2=0.0, n_basis=12, n_keep=5, K=1)
+    mm = om.build({"modes": [mode], "couplings": [], "beta": 10.0, "depth": 1,
+                   "decomp": "pade", "dt": 0.1})
+    k = np.arange(5)
+    q2 = np.diag(k + 0.5) + np.diag(np.sqrt((k[:-2] + 1) * (k[:-2] + 2)) / 2, 2)
+    q2 = q2 + np.triu(q2, 1).T
+    np.testing.assert_allclose(mm.H, np.diag(k + 0.5) + 0.01 * q2, atol=1e-13)
+
+
+# ------------------------------------------------------ RHS and RK4 ---------
+
+def _small_model():
+    p, _ = w.cfg1()
+    return om.build(p)
+
+
+def test_rhs_matches_assembled_liouvillian():
+    m = _small_model()
+    x = w.random_hierarchy(1, len(m.hier), m.d, seed=3)[0]
+    Lm = heom.liouvillian_matrix(m)
+    np.testing.assert_allclose(Lm @ x.reshape(-1), heom.rhs(m, x).reshape(-1), atol=1e-13)
+
+
+@pytest.mark.parametrize("cfg", ["cfg1", "cfg2small"])
+def test_adjoint_dot_product(cfg):
+    if cfg == "cfg1":
+        m = _small_model()
+    else:
+        p, _ = w.cfg2()
+        p["depth"] = 2
+        m = om.build(p)
+    x = w.random_hierarchy(1, len(m.hier), m.d, seed=5)[0]
+    y = w.random_hierarchy(1, len(m.hier), m.d, seed=6)[0]
+    lhs = np.sum(y * heom.rhs(m, x))
+    rhs_ = np.sum(heom.rhs(m, y, adjoint=True) * x)
+    assert abs(lhs - rhs_) < 1e-12 * abs(lhs)
+
+
+def test_rk4_is_fourth_order_taylor_polynomial():
+    # For a linear, time-independent L one classic RK4 step is exactly
+    # sum_{k<=4} (hL)^k / k! applied to the state.
+    m = _small_model()
+    x = w.random_hierarchy(1, len(m.hier), m.d, seed=7)[0].reshape(-1)
+    Lm = heom.liouvillian_matrix(m)
+    h = 0.3
+    acc, term = x.copy(), x.copy()
+    for k in range(1, 5):
+        term = h * (Lm @ term) / k
+        acc = acc + term
+    got = heom.rk4_step(m, x.reshape(len(m.hier), m.d, m.d), h=h).reshape(-1)
+    np.testing.assert_allclose(got, acc, atol=1e-12)
+
+
+def test_rk4_against_matrix_exponential():
+    m = _small_model()
+    rho = heom.ground_state_hierarchy(m)
+    t = 2.0
+    exact = sla.expm(heom.liouvillian_matrix(m).toarray() * t) @ rho.reshape(-1)
+    errs = []
+    for h in (0.1, 0.05):
+        steps = int(round(t / h))
+        y = rho
+        for _ in range(steps):
+            y = heom.rk4_step(m, y, h=h)
+        errs.append(np.max(np.abs(y.reshape(-1) - exact)))
+    assert errs[1] < 1e-8
+    assert errs[0] / errs[1] == pytest.approx(16.0, rel=0.15)
+
+
+def test_liouvillian_spectrum_stable_with_single_stationary_state():
+    m = _small_model()
+    ev = np.linalg.eigvals(heom.liouvillian_matrix(m).toarray())
+    assert np.max(ev.real) < 1e-12
+    assert int(np.sum(np.abs(ev) < 1e-9)) == 1
+    st = heom.stationary_state(m)
+    assert np.trace(st[0]).real == pytest.approx(1.0, abs=1e-13)
+    assert np.max(np.abs(heom.rhs(m, st))) < 1e-13
+
+
+# --------------------------------------------------------- invariants -------
+
+def test_trace_and_hermiticity_preserved():
+    m = _small_model()
+    rho = heom.ground_state_hierarchy(m)
+    rho = heom.propagate(m, rho, 200)
+    assert np.trace(rho[0]).real == pytest.approx(1.0, abs=1e-13)
+    assert abs(np.trace(rho[0]).imag) < 1e-14
+    herm = np.max(np.abs(rho - np.conj(np.swapaxes(rho, -1, -2))))
+    assert herm < 1e-14
+    X = heom.commutator(m.mu, rho)
+    assert abs(np.trace(X[0])) < 1e-14
+    X = heom.propagate(m, X, 50)
+    assert abs(np.trace(X[0])) < 1e-14
+
+
+def test_equilibrate_reaches_stationary_state_from_it():
+    # Starting at the stationary solution the residual check passes at once.
+    m = _small_model()
+    st = heom.stationary_state(m)
+    rho, steps, res = heom.equilibrate(m, 1e-12, 10, 0, 100, rho0=st)
+    assert steps == 10 and res < 1e-12
+    np.testing.assert_allclose(rho, st, atol=1e-12)
+
+
+def test_weak_coupling_equilibrium_is_gibbs():
+    # zeta -> 0 with Pade K=4: rho_0 of the stationary state -> exp(-beta H_S)/Z
+    # (Gibbs state of the bare system Hamiltonian; the counter-term makes the
+    # O(zeta) shift vanish at leading order in the populations).
+    mode = dict(omega=1.0, g3=-0.2, g4=0.02, V1=1.0, V2=0.0, zeta=0.002, gamma=0.5,
+                mu1=1.0, mu2=0.0, n_basis=12, n_keep=4, K=4)
+    p = {"modes": [mode], "couplings": [], "beta": 2.0, "depth": 2,
+         "decomp": "pade", "dt": 0.05}
+    m = om.build(p)
+    st = heom.stationary_state(m)
+    E = om.single_mode(mode).E
+    g = np.exp(-2.0 * (E - E[0]))
+    g /= g.sum()
+    pops = np.real(np.diag(st[0]))
+    assert np.max(np.abs(pops - g)) < 5e-3
+    assert abs(pops[1] - g[1]) / g[1] < 0.03
+
+
+# ------------------------------------------------------ closed forms --------
+
+def _unitary_response(H, D1, D2, D3, mu, rho0, t1, t2, t3):
+    E, U = np.linalg.eigh(H)
+
+    def G(X, t):
+        P = U @ np.diag(np.exp(-1j * E * t)) @ U.T
+        return P @ X @ P.conj().T
+
+    def cx(D, X):
+        return D @ X - X @ D
+
+    X = G(cx(D1, rho0), t1)
+    Y = G(cx(D2, X), t2)
+    Z = G(cx(D3, Y), t3)
+    return (1j) ** 3 * np.trace(mu @ Z)
+
+
+def test_no_bath_response_is_sum_over_states():
+    # zeta = 0: no ADO is ever populated and rho_0 evolves unitarily; R_P is
+    # the textbook closed form built from the eigenstates of H_S'.
+    p, _ = w.cfg2()
+    for mode in p["modes"]:
+        mode["zeta"] = 0.0
+        mode["n_keep"] = 3
+    p["depth"] = 1
+    p["dt"] = 0.05
+    m = om.build(p)
+    rho = heom.ground_state_hierarchy(m)
+    grid = {"n1": 4, "n3": 5, "steps_per_sample": 10, "t2_steps": [0, 7]}
+    R = heom.response_2d(m, rho, grid, pathways=("I", "II", "full"))
+    for i, t2s in enumerate(grid["t2_steps"]):
+        for pidx, pw in enumerate(("I", "II", "full")):
+            D1, D2, D3 = heom.pathway_dipoles(m, pw)
+            for j in range(4):
+                for k in range(5):
+                    ex = _unitary_response(m.H, D1, D2, D3, m.mu, rho[0],
+                                           0.5 * j, 0.05 * t2s, 0.5 * k)
+                    assert abs(R[i, pidx, j, k] - ex) < 1e-6 * (1 + abs(ex))
+
+
+def test_pure_dephasing_cumulant():
+    # Diagonal H and V: rho_ab(t) = rho_ab(0) exp(-i w_ab t)
+    #   * exp[-(v_a - v_b)(v_a g(t) - v_b conj(g(t)))],
+    # g(t) = sum_j c_j (exp(-nu_j t) + nu_j t - 1)/nu_j^2 (second-order
+    # cumulant, exact for a Gaussian bath); the hierarchy converges to it.
+    eps = np.array([0.0, 1.0, 1.9])
+    v = np.array([0.0, 0.6, 1.3])
+    nu, c = bath.drude_terms(0.1, 0.5, 2.0, 3, "pade")
+    errs = []
+    for L in (4, 8):
+        m = om.make_model(np.diag(eps), [np.diag(v)], np.zeros((3, 3)),
+                          [0] * len(nu), nu, c, L, dt=0.01)
+        rho = np.zeros((len(m.hier), 3, 3), dtype=complex)
+        rho[0] = 1.0 / 3.0
+        t = 3.0
+        rho = heom.propagate(m, rho, 300)
+        g = np.sum(c * (np.exp(-nu * t) + nu * t - 1) / nu ** 2)
+        ex = np.empty((3, 3), dtype=complex)
+        for a in range(3):
+            for b in range(3):
+                ex[a, b] = (1 / 3) * np.exp(-1j * (eps[a] - eps[b]) * t) * np.exp(
+                    -(v[a] - v[b]) * (v[a] * g - v[b] * np.conj(g)))
+        errs.append(np.max(np.abs(rho[0] - ex)))
+    assert errs[1] < 1e-7
+    assert errs[1] < errs[0]
+
+
+def _chi_brownian(t, omega0, gamma, zeta, V1):
+    # chi(s) = (s + gamma)/((s^2 + w0^2)(s + gamma) + V1^2 zeta gamma s)
+    poles = np.roots([1.0, gamma, omega0 ** 2 + V1 * V1 * zeta * gamma, omega0 ** 2 * gamma])
+    tot = 0.0
+    for i, s in enumerate(poles):
+        den = np.prod([s - q for k, q in enumerate(poles) if k != i])
+        tot = tot + (s + gamma) / den * np.exp(s * t)
+    return np.real(tot)
+
+
+def test_brownian_closed_form_worked_values():
+    assert _chi_brownian(1.0, 1, 0.2, 0.1, 1.0) == pytest.approx(0.8386119, abs=1e-7)
+    assert _chi_brownian(5.0, 1, 0.2, 0.1, 1.0) == pytest.approx(-0.9269534, abs=1e-7)
+    assert _chi_brownian(20.0, 1, 0.2, 0.1, 1.0) == pytest.approx(0.9288736, abs=1e-7)
+
+
+@pytest.mark.parametrize("beta,K,decomp", [(10.0, 2, "pade"), (10.0, 2, "matsubara"),
+                                           (3.0, 1, "pade")])
+def test_harmonic_linear_response_is_brownian_oscillator(beta, K, decomp):
+    # Harmonic mode, LL coupling, linear dipole: R1(t) = mu1^2 chi(t), the
+    # classical Brownian-oscillator response, independent of beta and K.
+    p = w.harmonic_pin(depth=4, K=K, dt=0.02, n_keep=6, beta=beta, decomp=decomp)
+    m = om.build(p)
+    R1 = heom.linear_response(m, heom.ground_state_hierarchy(m), 16, 50)
+    ex = np.array([_chi_brownian(t, 1.0, 0.2, 0.1, 1.0) for t in np.arange(16.0)])
+    assert np.max(np.abs(R1.imag)) < 1e-12
+    assert np.max(np.abs(R1.real - ex)) < 2e-5
+
+
+def test_harmonic_third_order_response_vanishes():
+    p = w.harmonic_pin(depth=3, K=2, dt=0.05, n_keep=6)
+    m = om.build(p)
+    grid = {"n1": 4, "n3": 4, "steps_per_sample": 20, "t2_steps": [0]}
+    R = heom.response_2d(m, heom.ground_state_hierarchy(m), grid, pathways=("I", "II", "full"))
+    R1 = heom.linear_response(m, heom.ground_state_hierarchy(m), 4, 20)
+    assert np.max(np.abs(R)) < 1e-6 * np.max(np.abs(R1))
+
+
+def test_full_response_is_real_and_sum_of_27_pathways():
+    p, _ = w.cfg1()
+    p["dt"] = 0.05
+    m = om.build(p)
+    rho = heom.propagate(m, heom.ground_state_hierarchy(m), 100)
+    grid = {"n1": 3, "n3": 3, "steps_per_sample": 10, "t2_steps": [4]}
+    R = heom.response_2d(m, rho, grid, pathways=("full",))[0, 0]
+    assert np.max(np.abs(R.imag)) < 1e-12 * np.max(np.abs(R))
+    mu0 = m.mu - m.mu_plus - m.mu_minus
+    parts = (m.mu_plus, m.mu_minus, mu0)
+    triples = [(a, b, c) for a in parts for b in parts for c in parts]
+    R27 = heom.response_2d(m, rho, grid, pathways=triples)[0]
+    np.testing.assert_allclose(R27.sum(0), R, atol=1e-13 * np.max(np.abs(R)))
+
+
+def test_response_invariant_under_eigenvector_signs():
+    p, _ = w.cfg2()
+    p["depth"] = 1
+    for mode in p["modes"]:
+        mode["n_keep"] = 3
+    p["dt"] = 0.1
+    modes = [om.single_mode(mm) for mm in p["modes"]]
+    m1 = om.build_from_modes(p, modes)
+    m2 = om.build_from_modes(p, [om.flip_sign(modes[0], 1), om.flip_sign(modes[1], 2)])
+    grid = {"n1": 3, "n3": 3, "steps_per_sample": 5, "t2_steps": [3]}
+    R1 = heom.response_2d(m1, heom.ground_state_hierarchy(m1), grid)
+    R2 = heom.response_2d(m2, heom.ground_state_hierarchy(m2), grid)
+    assert not np.allclose(m1.mu, m2.mu)
+    np.testing.assert_allclose(R1, R2, atol=1e-14)
+
+
+def test_depth_convergence():
+    p, _ = w.cfg1()
+    p["dt"] = 0.05
+    grid = {"n1": 6, "n3": 6, "steps_per_sample": 20, "t2_steps": [0]}
+    Rs = []
+    for L in (1, 2, 3, 4):
+        p["depth"] = L
+        m = om.build(p)
+        Rs.append(heom.response_2d(m, heom.ground_state_hierarchy(m), grid))
+    d = [np.max(np.abs(Rs[i + 1] - Rs[i])) for i in range(3)]
+    assert d[0] > d[1] > d[2]
+
+
+# ------------------------------------------------------------ spectra -------
+
+def test_spectrum_geometric_series():
+    # R[j, k] = exp(-i a t1_j - i b t3_k): each trapezoid-weighted sum is a
+    # finite geometric series, sum_{j<n} r^j - 1/2 = (1 - r^n)/(1 - r) - 1/2.
+    n1, n3, dts = 8, 6, 0.7
+    a, b = 1.1, -0.6
+    t1 = dts * np.arange(n1)
+    t3 = dts * np.arange(n3)
+    R = np.exp(-1j * a * t1)[:, None] * np.exp(-1j * b * t3)[None, :]
+    S = heom.pathway_spectrum(R, dts)
+    w1 = heom.frequency_grid(n1, dts)
+    w3 = heom.frequency_grid(n3, dts)
+
+    def geo(W, x, n):
+        r = np.exp(1j * (W - x) * dts)
+        return (1 - r ** n) / (1 - r) - 0.5
+
+    ex = np.imag(dts * dts * geo(w3[:, None], b, n3) * geo(w1[None, :], a, n1))
+    np.testing.assert_allclose(S, ex, atol=1e-12)
+    assert S.shape == (2 * n3, 2 * n1)
+
+
+@pytest.mark.slow
+def test_correlation_spectrum_sign_convention():
+    # Strongly anharmonic oscillator: the 0->1->0 diagonal peak (near w10, w10)
+    # is positive and the 0->1->2 peak (near w21 on the W3 axis) negative.
+    mode = dict(omega=1.0, g3=-0.6, g4=0.0, V1=0.5, V2=0.0, zeta=0.3, gamma=0.5,
+                mu1=1.0, mu2=0.0, n_basis=12, n_keep=4, K=2)
+    p = {"modes": [mode], "couplings": [], "beta": 10.0, "depth": 2,
+         "decomp": "pade", "dt": 0.05}
+    m = om.build(p)
+    grid = {"n1": 48, "n3": 48, "steps_per_sample": 20, "t2_steps": [0]}
+    R = heom.response_2d(m, heom.ground_state_hierarchy(m), grid)
+    S = heom.correlation_spectrum(R[0, 0], R[0, 1], 1.0)
+    wg = heom.frequency_grid(48, 1.0)
+    E = np.linalg.eigvalsh(m.H)
+    w10, w21 = E[1] - E[0], E[2] - E[1]
+    assert w10 - w21 > 0.15
+    imax = np.unravel_index(np.argmax(S), S.shape)
+    imin = np.unravel_index(np.argmin(S), S.shape)
+    step = wg[1] - wg[0]
+    assert S[imax] > 0 and S[imin] < 0
+    assert abs(wg[imax[0]] - w10) <= step and abs(wg[imax[1]] - w10) <= step
+    assert abs(wg[imin[0]] - w21) <= 1.5 * step and abs(wg[imin[1]] - w10) <= step

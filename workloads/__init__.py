@@ -1,0 +1,19 @@
+"""Seeded synthetic inputs shared by the CPU oracle and the HIP path.
+
+This package holds parameter draws and random test states only.  It contains
+none of the method's arithmetic (no Hamiltonians, bath terms or propagation):
+both sides read the same plain dictionaries and arrays produced here.
+"""
+
+from .configs import (  # noqa: F401
+    FS_PER_TIME_UNIT,
+    cfg1,
+    cfg2,
+    cfg3,
+    cfg4_instances,
+    cfg5,
+    harmonic_pin,
+    fs_to_steps,
+    response_grid,
+)
+from .states import random_hierarchy  # noqa: F401

@@ -1,0 +1,171 @@
+"""Seeded parameter sets for the multi-mode anharmonic Brownian (MAB) model.
+
+Every function returns a plain JSON-serialisable dictionary.  Units: hbar = 1,
+energies in units of omega0 (the harmonic frequency of the first mode), time in
+1/omega0, temperature given as beta*hbar*omega0.  Coordinates are dimensionless
+and the bath formulas take m_s = 1.
+
+Parameter dictionary layout (both the oracle and the C-ABI binding read it):
+
+    {"modes": [{"omega", "g3", "g4", "V1", "V2", "zeta", "gamma",
+                "mu1", "mu2", "n_basis", "n_keep", "K"}, ...],
+     "couplings": [{"s", "t", "g_st", "g_s2t", "g_st2", "mu_st"}, ...],
+     "beta", "depth", "decomp" ("pade" | "matsubara"), "dt"}
+
+Mode keys follow the model of Sec. II.A: the potential
+omega*q^2/2 + g3 q^3/3! + g4 q^4/4! (Eq. Potentials plus an optional quartic
+term), the system-bath coupling V(q) = V1 q + V2 q^2/2 (Eq. h_int, LL and SL
+parts), the Drude bath (zeta, gamma) of Eq. drude with K low-temperature terms,
+and the dipole mu1 q + mu2 q^2/2 (Eq. NLdip, diagonal part).  Coupling keys
+are the coefficients of Eq. Potential ss' (g_st q_s q_t, g_s2t q_s^2 q_t / 6,
+g_st2 q_s q_t^2 / 6) and the cross dipole mu_st q_s q_t.
+
+The workloads stand in for the paper's water models (Tables I-III), which are
+not a public benchmark: they keep the structure (two stretches plus a bend,
+cubic/quartic anharmonicity, bilinear and Fermi couplings, Drude baths, a
+handful of levels per mode) with seeded draws.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# 1/omega0 in femtoseconds for omega0 = 3470 cm^-1 (the symmetric stretch).
+FS_PER_TIME_UNIT = 1.0e15 / (2.0 * math.pi * 2.99792458e10 * 3470.0)
+
+
+def fs_to_steps(t_fs: float, dt: float) -> int:
+    """Number of RK4 steps of size dt closest to t_fs femtoseconds."""
+    return int(round(t_fs / FS_PER_TIME_UNIT / dt))
+
+
+def _mode(rng, omega, n_keep, K, zeta=0.1, gamma=0.2, mu1=1.0, mu2=0.2,
+          n_basis=12):
+    g3 = float(rng.uniform(-0.3, -0.1))
+    g4 = float(rng.uniform(0.01, 0.05))
+    V1 = float(rng.uniform(0.5, 1.0))
+    V2 = float(rng.uniform(0.0, 0.2))
+    return {"omega": float(omega), "g3": g3, "g4": g4, "V1": V1, "V2": V2,
+            "zeta": float(zeta), "gamma": float(gamma), "mu1": float(mu1),
+            "mu2": float(mu2), "n_basis": int(n_basis), "n_keep": int(n_keep),
+            "K": int(K)}
+
+
+def _coupling(s, t, g_st=0.0, g_s2t=0.0, g_st2=0.0, mu_st=0.0):
+    return {"s": int(s), "t": int(t), "g_st": float(g_st),
+            "g_s2t": float(g_s2t), "g_st2": float(g_st2),
+            "mu_st": float(mu_st)}
+
+
+def response_grid(n, steps_per_sample, t2_steps):
+    """t1/t3 grid of n samples spaced steps_per_sample RK4 steps apart."""
+    return {"n1": int(n), "n3": int(n), "steps_per_sample": int(steps_per_sample),
+            "t2_steps": [int(s) for s in t2_steps]}
+
+
+def cfg1(seed: int = 0):
+    """One anharmonic mode, 6 kept levels, K=2 Matsubara terms, depth 4.
+
+    35 ADOs of 6x6; dt = 0.01; 32x32 grid at t2 = 0.
+    """
+    rng = np.random.default_rng(seed)
+    m = _mode(rng, 1.0, n_keep=6, K=2, mu1=1.0, mu2=0.2)
+    params = {"modes": [m], "couplings": [], "beta": 10.0, "depth": 4,
+              "decomp": "matsubara", "dt": 0.01}
+    return params, response_grid(32, 100, [0])
+
+
+def cfg2(seed: int = 0):
+    """Two coupled modes (omega 1.0 : 0.45), 5x5 states, K=2 Pade, depth 5.
+
+    462 ADOs of 25x25; dt = 0.1; 64x64 grid at t2 in {0, 100 fs}.
+    """
+    rng = np.random.default_rng(seed)
+    modes = [_mode(rng, 1.0, n_keep=5, K=2), _mode(rng, 0.45, n_keep=5, K=2)]
+    g12 = float(rng.uniform(0.0, 0.05))
+    g122 = float(rng.uniform(0.0, 0.05))
+    couplings = [_coupling(0, 1, g_st=g12, g_st2=g122, mu_st=0.02)]
+    params = {"modes": modes, "couplings": couplings, "beta": 10.0,
+              "depth": 5, "decomp": "pade", "dt": 0.1}
+    return params, response_grid(64, 10, [0, fs_to_steps(100.0, 0.1)])
+
+
+def cfg3(seed: int = 0, depth: int = 6):
+    """Water-like three-mode model: sym/asym stretch and bend (1 : 1.03 : 0.44).
+
+    4x4x5 = 80 states, K=2 Pade per mode (9 exponential terms), depth 6
+    (5005 ADOs of 80x80); dt = 0.1; 128x128 grid at t2 = 0, 50, 100, 200 fs.
+    """
+    rng = np.random.default_rng(seed)
+    modes = [_mode(rng, 1.0, n_keep=4, K=2), _mode(rng, 1.03, n_keep=4, K=2),
+             _mode(rng, 0.44, n_keep=5, K=2)]
+    g01, g02, g12 = (float(x) for x in rng.uniform(0.0, 0.05, size=3))
+    f02, f12 = (float(x) for x in rng.uniform(0.0, 0.05, size=2))
+    couplings = [_coupling(0, 1, g_st=g01, mu_st=0.02),
+                 _coupling(0, 2, g_st=g02, g_st2=f02, mu_st=0.02),
+                 _coupling(1, 2, g_st=g12, g_st2=f12, mu_st=0.02)]
+    params = {"modes": modes, "couplings": couplings, "beta": 10.0,
+              "depth": int(depth), "decomp": "pade", "dt": 0.1}
+    t2 = [0] + [fs_to_steps(t, 0.1) for t in (50.0, 100.0, 200.0)]
+    return params, response_grid(128, 10, t2)
+
+
+def _hierarchy_size(n_terms: int, depth: int) -> int:
+    # size of the triangular index set {n in N^M : |n| <= L}; used only for
+    # the redraw rule of the mixed-instance workload below
+    return math.comb(n_terms + depth, depth)
+
+
+def cfg4_instances(n_instances: int = 64, seed: int = 0):
+    """Uneven batch: 1-3 modes (6, 25 or 80 states), K in {1,2}, depth 3..6.
+
+    Draws whose hierarchy has fewer than 35 ADOs are redrawn.  Each instance
+    has a 64x64 grid at t2 = 0 with dt = 0.1.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n_instances:
+        n_modes = int(rng.integers(1, 4))
+        Ks = [int(k) for k in rng.integers(1, 3, size=n_modes)]
+        depth = int(rng.integers(3, 7))
+        if _hierarchy_size(sum(k + 1 for k in Ks), depth) < 35:
+            continue
+        keep = {1: [6], 2: [5, 5], 3: [4, 4, 5]}[n_modes]
+        omegas = {1: [1.0], 2: [1.0, 0.45], 3: [1.0, 1.03, 0.44]}[n_modes]
+        modes = [_mode(rng, w, n_keep=k, K=K) for w, k, K in zip(omegas, keep, Ks)]
+        couplings = []
+        for s in range(n_modes):
+            for t in range(s + 1, n_modes):
+                couplings.append(_coupling(s, t, g_st=float(rng.uniform(0, 0.05)),
+                                           g_st2=float(rng.uniform(0, 0.05)),
+                                           mu_st=0.02))
+        out.append(({"modes": modes, "couplings": couplings, "beta": 10.0,
+                     "depth": depth, "decomp": "pade", "dt": 0.1},
+                    response_grid(64, 10, [0])))
+    return out
+
+
+def cfg5(seed: int = 0):
+    """Gradient workload: the three-mode depth-6 model, 64x64 grid, t2 in {0, 100 fs}.
+
+    Returns (params, grid, theta_scale) where theta_scale holds the +-5%
+    perturbation factors of the 12 fitted parameters (g3 x3, g4 x3, bilinear
+    scale, Fermi scale, V1, V2, zeta, gamma) used to make the target spectrum.
+    """
+    params, _ = cfg3(seed)
+    rng = np.random.default_rng(seed + 1000)
+    r = rng.choice([-1.0, 1.0], size=12)
+    grid = response_grid(64, 10, [0, fs_to_steps(100.0, 0.1)])
+    return params, grid, [float(1.0 + 0.05 * x) for x in r]
+
+
+def harmonic_pin(omega=1.0, zeta=0.1, gamma=0.2, V1=1.0, beta=10.0, K=2,
+                 depth=4, n_keep=6, decomp="pade", dt=0.01):
+    """Harmonic mode with linear (LL) coupling and a linear dipole."""
+    m = {"omega": omega, "g3": 0.0, "g4": 0.0, "V1": V1, "V2": 0.0,
+         "zeta": zeta, "gamma": gamma, "mu1": 1.0, "mu2": 0.0,
+         "n_basis": 12, "n_keep": n_keep, "K": K}
+    return {"modes": [m], "couplings": [], "beta": beta, "depth": depth,
+            "decomp": decomp, "dt": dt}
