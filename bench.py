@@ -1,0 +1,169 @@
+"""Benchmark of the HEOM-2DVS hot path on one MI355X.
+
+Workload (default): the water-like three-mode model (4x4x5 = 80 states,
+K=2 Pade terms per mode, depth L=6: 5005 ADOs), 128 trajectories -- the t1
+samples of the 128x128 grid -- propagated together in FP32 by fixed-step RK4:
+the batched t2/t3 propagation that dominates a 2D spectrum.  One "step" is one
+RK4 step of the whole batch (4 fused RHS launches).  value = ADO-updates/s =
+trajectories x ADOs x steps / wall time.
+
+Also reported: seconds per 2D spectrum (t2 = 0, full 128x128 grid, FP32
+propagation with FP64 pairing) measured end to end; the roofline of the
+dominant kernel from HIP-event timings of its launches inside the timed
+region; and the CPU oracle's rate on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS = {  # MI355X published dense peaks
+    "fp32_tflops": 157.3,
+    "fp64_tflops": 78.6,
+    "hbm_gbs": 8000.0,
+}
+
+
+def algorithmic_flops_per_rhs(model):
+    """Flops of one RHS evaluation of every ADO of one trajectory.
+
+    Per ADO: H commutator 8 d^3 (complex x real, both sides); V_s products
+    8 d^2 sum_s d_s; neighbour combination 2 d^2 per upper neighbour (unit
+    coefficient, shared by both sides) and 16 d^2 per lower neighbour (complex
+    coefficient, two sides); damping 2 d^2; RK4 stage update 4 d^2.
+    """
+    ops = model.operators()
+    n = ops["ado_n"]
+    d = model.d
+    depth = n.sum(1)
+    n_up = np.where(depth < model.depth, n.shape[1], 0).sum()
+    n_down = int((n > 0).sum())
+    per_ado = 8 * d ** 3 + 8 * d * d * sum(model.dims) + 6 * d * d
+    return per_ado * model.n_ado + d * d * (2 * n_up + 16 * n_down)
+
+
+def cpu_baseline(params, budget_s=30.0):
+    """Oracle rate on a bounded sample: RHS evaluations of one trajectory."""
+    from oracle import heom as oh
+    from oracle import model as om
+    import workloads as w
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    o = om.build(params)
+    x = w.random_hierarchy(1, len(o.hier), o.d, seed=1)[0]
+    t0 = time.perf_counter()
+    n_rhs = 0
+    while True:
+        oh.rhs(o, x)
+        n_rhs += 1
+        if time.perf_counter() - t0 > budget_s / 3 or n_rhs >= 4:
+            break
+    dt = (time.perf_counter() - t0) / n_rhs
+    rate = len(o.hier) / (4.0 * dt)  # one ADO-update = one RK4 step = 4 RHS
+    return {"value": rate, "unit": "ADO-updates/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{n_rhs} oracle RHS evaluation(s) of one trajectory of the "
+                      f"{len(o.hier)}-ADO model ({dt:.1f} s each); 4 RHS = 1 RK4 step"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=128)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--depth", type=int, default=6)
+    ap.add_argument("--spectrum", type=int, default=1, help="also time one full 2D spectrum")
+    ap.add_argument("--eq-steps", type=int, default=200)
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the path shards into independent "
+              "trajectory batches (see DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2601_20550_amd as P
+    import workloads as w
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    params, grid = w.cfg3(depth=args.depth)
+    stream = torch.cuda.current_stream()
+    m = P.heom_model_build(params, stream=stream.cuda_stream)
+    B = args.batch
+    s = P.State(m, B, args.precision)
+    s.set_ground()
+    P.heom_propagate(m, s, args.warmup)
+    torch.cuda.synchronize()
+
+    P.heom_timing_enable(m, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.heom_propagate(m, s, args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k_ms, n_launch, upd = P.heom_timing_read(m)
+    P.heom_timing_enable(m, False)
+
+    ado_updates = B * m.n_ado * args.steps
+    value = ado_updates / wall
+    avg_launch_s = k_ms / 1e3 / max(n_launch, 1)
+    flops_launch = algorithmic_flops_per_rhs(m) * B
+    achieved = flops_launch / avg_launch_s / 1e12
+    peak = PEAKS["fp32_tflops"] if args.precision == "fp32" else PEAKS["fp64_tflops"]
+
+    line = {
+        "metric": "ADO-updates/s + s per 2D spectrum (3-mode, L=6); FP32/batched vs FP64",
+        "value": value,
+        "unit": "ADO-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic (seeded water-like 3-mode model; no trained inputs)",
+        "config": {"workload": f"3-mode MAB HEOM, 80 states, K=2 Pade x3, depth {args.depth} "
+                               f"({m.n_ado} ADOs), {B} trajectories batched, RK4 dt=0.1",
+                   "n_ado": m.n_ado, "d": m.d, "trajectories": B},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "rhs_generic_kernel (fused RHS + RK4 stage)",
+                     "avg_launch_ms": avg_launch_s * 1e3, "launches": n_launch},
+    }
+
+    if args.spectrum:
+        rho, eq_steps, eq_res = P.heom_equilibrate(m, tol=0.0, check_every=args.eq_steps,
+                                                   min_steps=0, max_steps=args.eq_steps)
+        g1 = dict(grid)
+        g1["t2_steps"] = [0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        R = P.heom_response_2d(m, rho, g1, args.precision, "adjoint")
+        S = P.heom_spectrum_2d(R[0, 0], R[0, 1], grid["steps_per_sample"] * params["dt"])
+        torch.cuda.synchronize()
+        line["s_per_2d_spectrum"] = time.perf_counter() - t0
+        line["spectrum_config"] = {"t2": 0, "grid": [g1["n1"], g1["n3"]], "method": "adjoint",
+                                   "equilibration_steps": eq_steps, "finite": bool(np.isfinite(S).all())}
+    del s
+    if args.cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(params)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

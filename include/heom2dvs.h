@@ -1,0 +1,239 @@
+/*
+ * heom2dvs.h -- C ABI of the MI355X (gfx950) HEOM-2DVS library.
+ *
+ * The library time-steps the hierarchical equations of motion (HEOM) of the
+ * multi-mode anharmonic Brownian (MAB) oscillator model and evaluates linear
+ * and third-order (2D IR) response functions and the 2D correlation
+ * spectrum, following Hoshino & Tanimura, arXiv:2601.20550:
+ *   model            Sec. II.A, Eqs. (Total Hamiltonian)-(h_int), (NLdip),
+ *                    (counter1)-(sys_interaction)
+ *   bath terms       Sec. II.B, Eqs. (drude), (L1), (L2), (counterterm),
+ *                    (Pade1), (Pade2)
+ *   HEOM             Sec. II.B, Eq. (HEOM_DB)
+ *   responses        Sec. II.C, Eqs. (R1), (RFTIRI), (echo), (virtual-echo)
+ *   spectra          Sec. II.C, Eqs. (2D-rephasing), (2D-nonrephasing),
+ *                    (correlation-spectrum)
+ *   integrator       Sec. III (fourth-order Runge-Kutta, fixed step)
+ *
+ * Conventions
+ *   Units: hbar = 1; energies in units of omega0 (harmonic frequency of the
+ *   reference mode); time in 1/omega0; beta is beta*hbar*omega0; m_s = 1.
+ *   Product basis: mode 0 is the slowest index; each mode keeps the n_keep
+ *   lowest eigenstates of its single-mode Hamiltonian (Sec. II.A).
+ *   Hierarchy: ADOs n = (n_j), one entry per exponential bath term j
+ *   (terms of mode 0 first, k = 0..K within a mode), truncated to
+ *   |n| <= depth, ordered by depth and then ascending lexicographically.
+ *   Host arrays of complex numbers are interleaved (re, im) doubles.
+ *   A host hierarchy array has layout [n_traj][n_ado][d][d] complex, row-major.
+ *
+ * Errors: every int-returning call returns HEOM_OK (0) or a negative code;
+ * heom_last_error() returns a thread-local message for the last failure.
+ * No C++ exception crosses the ABI.  Pointers named *_out are caller-owned
+ * host memory unless stated otherwise.  Objects returned through ** are owned
+ * by the caller and released with the matching *_free call.
+ */
+#ifndef HEOM2DVS_H
+#define HEOM2DVS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HEOM_OK = 0,
+  HEOM_ERR_PARAM = -1,     /* invalid argument or parameter set          */
+  HEOM_ERR_OOM = -2,       /* device allocation failed                   */
+  HEOM_ERR_UNSTABLE = -3,  /* non-finite values during propagation       */
+  HEOM_ERR_NOCONV = -4,    /* equilibration above tolerance at max_steps */
+  HEOM_ERR_HIP = -5,       /* HIP runtime error (message has details)    */
+  HEOM_ERR_STATE = -6      /* object mismatch (model/state/precision)    */
+};
+
+typedef enum { HEOM_FP64 = 0, HEOM_FP32 = 1 } heom_precision;
+typedef enum { HEOM_PADE = 0, HEOM_MATSUBARA = 1 } heom_decomp;
+/* Operators that the dipole/trace calls can apply. */
+typedef enum { HEOM_OP_MU = 0, HEOM_OP_MU_PLUS = 1, HEOM_OP_MU_MINUS = 2 } heom_operator;
+/* How heom_response_2d obtains the t3 dependence.
+ * HEOM_RESP_DIRECT : the paper's order -- every t1 snapshot is propagated
+ *                    over t2 and t3 and the trace is sampled (Sec. II.C).
+ * HEOM_RESP_ADJOINT: the t3 propagation is replaced by one propagation of
+ *                    the detection functional tr(mu .) under the transposed
+ *                    HEOM; R is then the bilinear pairing of the two sets of
+ *                    hierarchies.  Identical in exact arithmetic, including
+ *                    the RK4 discretisation. */
+typedef enum { HEOM_RESP_DIRECT = 0, HEOM_RESP_ADJOINT = 1 } heom_resp_method;
+
+/* One vibrational mode s (Sec. II.A, II.B):
+ *   H_A = omega (p^2 + q^2)/2 + g3 q^3/3! + g4 q^4/4!   (Eq. Potentials; g4 optional)
+ *   V_s(q) = V1 q + V2 q^2/2                             (Eq. h_int, LL + SL)
+ *   Drude bath (zeta, gamma) with K low-temperature terms (Eqs. drude, Pade1/2)
+ *   dipole mu1 q + mu2 q^2/2                             (Eq. NLdip, s = s')
+ *   n_basis harmonic levels are diagonalised, n_keep eigenstates are kept. */
+typedef struct {
+  double omega, g3, g4, V1, V2, zeta, gamma, mu1, mu2;
+  int n_basis, n_keep, K;
+} heom_mode;
+
+/* Mode-mode coupling (Eq. Potential ss') and cross dipole (Eq. NLdip), s < t:
+ *   g_st q_s q_t + (g_s2t q_s^2 q_t + g_st2 q_s q_t^2)/6 ;  mu_st q_s q_t */
+typedef struct {
+  int s, t;
+  double g_st, g_s2t, g_st2, mu_st;
+} heom_coupling;
+
+typedef struct {
+  int n_modes;                      /* 1..4                                  */
+  const heom_mode* modes;
+  int n_couplings;
+  const heom_coupling* couplings;
+  double beta;                      /* beta * hbar * omega0                  */
+  int depth;                        /* hierarchy depth L                     */
+  int decomp;                       /* heom_decomp                           */
+  double dt;                        /* RK4 step (1/omega0)                   */
+} heom_params;
+
+typedef struct {
+  int d;                            /* product-basis dimension               */
+  int n_ado;                        /* number of ADOs                        */
+  int n_terms;                      /* M = sum_s (K_s + 1)                   */
+  int n_modes;
+  int dims[4];                      /* kept levels per mode                  */
+  int depth;
+  double dt;
+} heom_info;
+
+/* t1/t3 sampling grid and t2 values of a third-order response.
+ * t1_j = j * steps_per_sample * dt, t3_k = k * steps_per_sample * dt and
+ * t2 = t2_steps[i] * dt; t2_steps must be non-decreasing. */
+typedef struct {
+  int n1, n3, steps_per_sample;
+  int n_t2;
+  const int* t2_steps;
+} heom_grid;
+
+typedef struct heom_model heom_model;
+typedef struct heom_state heom_state;
+
+/* ------------------------------------------------------------ general -- */
+const char* heom_last_error(void);
+/* Device allocator hook (e.g. a framework's caching allocator).  NULL
+ * functions restore hipMalloc/hipFree.  Applies to later allocations. */
+typedef void* (*heom_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*heom_free_fn)(void* ptr, void* ctx);
+int heom_set_allocator(heom_alloc_fn alloc, heom_free_fn release, void* ctx);
+/* Device properties used by the launch heuristics: CU count and LDS bytes per
+ * workgroup of the current device. */
+int heom_device_query(int* cu_count, int* lds_bytes, char* name_out, int name_len);
+
+/* -------------------------------------------------------------- model -- */
+/* Builds the operators of Sec. II.A in the product eigenbasis, the bath terms
+ * of Sec. II.B and the hierarchy tables (host, FP64), then uploads them to the
+ * current device.  `hip_stream` (a hipStream_t, may be NULL for the null
+ * stream) is used by every later call on this model.
+ * Errors: HEOM_ERR_PARAM for n_keep > n_basis, n_modes outside 1..4, product
+ * dimension > 128, |gamma^2 - nu_k^2| < 1e-12 (Eq. Pade1 singular), depth < 0,
+ * dt <= 0, couplings with s >= t or out of range. */
+int heom_model_build(const heom_params* params, void* hip_stream, heom_model** out);
+/* Host part only (no device memory): for inspecting the operators. */
+int heom_model_build_host(const heom_params* params, heom_model** out);
+void heom_model_free(heom_model* model);
+int heom_model_info(const heom_model* model, heom_info* out);
+/* Copies the host FP64 operators.  Any pointer may be NULL.
+ *   H, mu, mu_plus, mu_minus: [d][d];  v: per mode [dims[s]][dims[s]] packed
+ *   one after another;  nu: [n_terms];  c: [n_terms] complex;
+ *   ado_n: [n_ado][n_terms] ints;  term_mode: [n_terms] ints. */
+int heom_model_operators(const heom_model* model, double* H, double* mu, double* mu_plus,
+                         double* mu_minus, double* v, double* nu, double* c, int* ado_n,
+                         int* term_mode);
+
+/* -------------------------------------------------------------- state -- */
+/* A device hierarchy of n_traj independent trajectories (n_traj x n_ado
+ * complex d x d matrices) in the given precision, zero-initialised. */
+int heom_state_create(heom_model* model, int n_traj, int precision, heom_state** out);
+void heom_state_free(heom_state* state);
+int heom_state_shape(const heom_state* state, int* n_traj, int* precision);
+/* host [n_traj][n_ado][d][d] complex <-> device (converted to the state's precision) */
+int heom_state_upload(heom_state* state, const double* host);
+int heom_state_download(const heom_state* state, double* host_out);
+/* Same for trajectories first .. first+count-1 only (host [count][n_ado][d][d]). */
+int heom_state_upload_range(heom_state* state, int first, int count, const double* host);
+int heom_state_download_range(const heom_state* state, int first, int count, double* host_out);
+/* rho_{n=0} = |0><0| and every other ADO zero, for every trajectory
+ * (factorised initial condition of Sec. II.C). */
+int heom_state_set_ground(heom_state* state);
+/* dst <- src, converting precision; trajectory counts must match. */
+int heom_state_copy(heom_state* dst, const heom_state* src);
+
+/* ---------------------------------------------------------- hot path -- */
+/* out = L in (adjoint = 0) or L^T in (adjoint = 1) for every trajectory,
+ * L being the HEOM generator of Eq. (HEOM_DB).  L^T is the transpose for the
+ * bilinear pairing <A, X> = sum_n sum_ab A_n[a,b] X_n[a,b]. */
+int heom_rhs(heom_model* model, const heom_state* in, heom_state* out, int adjoint);
+/* n_steps fixed-step fourth-order Runge-Kutta steps of d rho/dt = L rho (or
+ * L^T rho) in place.  The step is evaluated as y + h L(y + h/2 L(y + h/3 L(y
+ * + h/4 L y))), which equals the classic four-stage scheme for this linear,
+ * time-independent generator.  HEOM_ERR_UNSTABLE if the state becomes
+ * non-finite (checked at the end). */
+int heom_propagate(heom_model* model, heom_state* state, int n_steps, int adjoint);
+/* X <- D^x X = D X - X D on every ADO (transpose = 0), or
+ * X <- (D^T)^x X (transpose = 1), D chosen by `op` (heom_operator). FP64
+ * arithmetic on either precision. */
+int heom_apply_dipole(heom_model* model, heom_state* state, int op, int transpose);
+/* out[b] = tr(D rho_{b, n=0}) for each trajectory b, FP64 accumulation;
+ * out: [n_traj] complex. */
+int heom_trace(heom_model* model, const heom_state* state, int op, double* out);
+/* max over trajectories, ADOs and elements of |(L rho)| (FP64 value). */
+int heom_residual(heom_model* model, const heom_state* state, double* out);
+
+/* Equilibration (Sec. II.C, first two steps of the recipe): from
+ * rho_{n=0} = |0><0| propagate in FP64; after every check_every steps (once
+ * min_steps are done) evaluate the residual max|L rho|; stop at the first
+ * check <= tol or at max_steps.  Returns a new FP64 state with one
+ * trajectory.  HEOM_ERR_NOCONV is returned (with the state still written)
+ * when max_steps is reached above tol and require_convergence != 0. */
+int heom_equilibrate(heom_model* model, double tol, int check_every, int min_steps,
+                     int max_steps, int require_convergence, heom_state** rho_eq_out,
+                     int* steps_out, double* residual_out);
+
+/* Linear response (Eq. R1): R1(t_k) = i tr{mu G(t_k) mu^x rho_eq},
+ * t_k = k * steps_per_sample * dt, k = 0..n-1.  R_out: [n] complex. */
+int heom_linear_response(heom_model* model, const heom_state* rho_eq, int n,
+                         int steps_per_sample, int precision, double* R_out);
+
+/* Third-order responses of the rephasing (I: k3+k2-k1) and non-rephasing
+ * (II: k3-k2+k1) pathways (Eqs. echo, virtual-echo) with the rotating-wave
+ * split of the dipole: (D1,D2,D3) = (mu-, mu+, mu+) for I and (mu+, mu-, mu+)
+ * for II, mu+ keeping the elements that raise the total number of kept quanta.
+ * R = i^3 tr{mu G(t3) D3^x G(t2) D2^x G(t1) D1^x rho_eq}.
+ * rho_eq: FP64 state with one trajectory.  precision selects the arithmetic of
+ * the propagations (dipoles, traces and pairings are FP64).  max_batch bounds
+ * the number of trajectories propagated together (0 = automatic from free
+ * device memory).  R_out: [n_t2][2][n1][n3] complex. */
+int heom_response_2d(heom_model* model, const heom_state* rho_eq, const heom_grid* grid,
+                     int precision, int method, int max_batch, double* R_out);
+
+/* 2D correlation spectrum (Eq. correlation-spectrum) from the two pathway
+ * responses, computed on the device in FP64: trapezoid weights (1/2 at t=0),
+ * zero padding to 2n, Omega_m = 2 pi m/(2 n dt_s), m = -n..n-1,
+ * S_P(W3,W1) = Im sum_jk w_j w_k dt_s^2 exp(i W3 t3_k + i W1 t1_j) R_P[j][k],
+ * S_C(W3,W1) = -[S_I(W3,-W1) + S_II(W3,W1)] (sign fixed so the 0->1->0 peak
+ * is positive).  R_I, R_II: [n1][n3] complex host arrays; S_out:
+ * [2 n3][2 n1] doubles (rows W3, columns W1). */
+int heom_spectrum_2d(const double* R_I, const double* R_II, int n1, int n3, double dt_s,
+                     double* S_out);
+
+/* ------------------------------------------------------- measurement -- */
+/* While enabled, every launch of the fused RHS/RK4-stage kernel on this model
+ * is bracketed by HIP events on the model's stream; heom_timing_read returns
+ * the summed kernel time (ms), the number of launches and the number of
+ * ADO-matrix updates they performed, then resets the counters. */
+int heom_timing_enable(heom_model* model, int enable);
+int heom_timing_read(heom_model* model, double* total_ms, long long* launches,
+                     long long* ado_updates);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HEOM2DVS_H */

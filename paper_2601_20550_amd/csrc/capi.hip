@@ -1,0 +1,959 @@
+// C ABI of the HEOM-2DVS library: object management, device memory and the
+// propagation drivers (equilibration, linear and third-order responses).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <type_traits>
+#include <utility>
+#include <vector>
+
+#include "heom2dvs.h"
+#include "kernels.h"
+#include "model.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct HeomError : std::runtime_error {
+  int code;
+  HeomError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+heom_alloc_fn g_alloc = nullptr;
+heom_free_fn g_free = nullptr;
+void* g_alloc_ctx = nullptr;
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    hipGetLastError();
+    throw HeomError(HEOM_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+void* dev_alloc(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  void* p = nullptr;
+  if (g_alloc) {
+    p = g_alloc(bytes, g_alloc_ctx);
+    if (!p) throw HeomError(HEOM_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    return p;
+  }
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    hipGetLastError();
+    throw HeomError(HEOM_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+  }
+  return p;
+}
+
+void dev_free(void* p) {
+  if (!p) return;
+  if (g_alloc && g_free) {
+    g_free(p, g_alloc_ctx);
+    return;
+  }
+  (void)hipFree(p);
+}
+
+// Owning device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t b) : p(dev_alloc(b)), bytes(b) {}
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      dev_free(p);
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
+  ~DevBuf() { dev_free(p); }
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    f();
+    return HEOM_OK;
+  } catch (const HeomError& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::invalid_argument& e) {
+    g_last_error = e.what();
+    return HEOM_ERR_PARAM;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return HEOM_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return HEOM_ERR_HIP;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return HEOM_ERR_HIP;
+  }
+}
+
+template <typename T>
+DevBuf upload_vec(const std::vector<T>& v, hipStream_t st) {
+  DevBuf b(v.size() * sizeof(T));
+  if (!v.empty()) hip_check(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st),
+                            "upload");
+  hip_check(hipStreamSynchronize(st), "upload sync");
+  return b;
+}
+
+}  // namespace
+
+struct heom_model {
+  heom::HostModel hm;
+  bool has_device = false;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int lds_limit = 65536;
+  // device copies
+  DevBuf H64, H32, v64, v32, g64, g32, mu64[3];
+  DevBuf nb_ptr[2], nb_idx[2], nb_a64[2], nb_a32[2];
+  heom::DevOps<double> ops64[2];
+  heom::DevOps<float> ops32[2];
+  // scratch: two hierarchy-sized work buffers per precision, grown on demand
+  DevBuf scratch[2];
+  DevBuf red_partial, red_result;
+  // kernel timing
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  size_t events_used = 0;
+  long long launches = 0, ado_updates = 0;
+
+  ~heom_model() {
+    for (auto& e : events) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+  }
+  long long traj_elems() const { return static_cast<long long>(hm.n_ado) * 2 * hm.d * hm.d; }
+};
+
+struct heom_state {
+  heom_model* model = nullptr;
+  int n_traj = 0;
+  int precision = HEOM_FP64;
+  DevBuf buf;
+  long long n_elems() const { return static_cast<long long>(n_traj) * model->traj_elems(); }
+  size_t elem_size() const { return precision == HEOM_FP64 ? sizeof(double) : sizeof(float); }
+};
+
+namespace {
+
+void require_device(const heom_model* m) {
+  if (!m) throw HeomError(HEOM_ERR_PARAM, "null model");
+  if (!m->has_device) throw HeomError(HEOM_ERR_STATE, "model has no device data (built with heom_model_build_host)");
+}
+
+void require_state(const heom_model* m, const heom_state* s) {
+  if (!s) throw HeomError(HEOM_ERR_PARAM, "null state");
+  if (s->model != m) throw HeomError(HEOM_ERR_STATE, "state belongs to another model");
+}
+
+heom_params copy_check(const heom_params* p) {
+  if (!p) throw HeomError(HEOM_ERR_PARAM, "null params");
+  return *p;
+}
+
+void upload_model(heom_model* m) {
+  const auto& hm = m->hm;
+  hipStream_t st = m->stream;
+  std::vector<float> tmp;
+  auto f32 = [&](const std::vector<double>& v) {
+    tmp.assign(v.begin(), v.end());
+    return upload_vec(tmp, st);
+  };
+  m->H64 = upload_vec(hm.H, st);
+  m->H32 = f32(hm.H);
+  std::vector<double> vpack;
+  int v_off[4] = {0, 0, 0, 0};
+  for (int s = 0; s < hm.n_modes; ++s) {
+    v_off[s] = static_cast<int>(vpack.size());
+    vpack.insert(vpack.end(), hm.v[s].begin(), hm.v[s].end());
+  }
+  m->v64 = upload_vec(vpack, st);
+  m->v32 = f32(vpack);
+  m->g64 = upload_vec(hm.gamma_sum, st);
+  m->g32 = f32(hm.gamma_sum);
+  m->mu64[HEOM_OP_MU] = upload_vec(hm.mu, st);
+  m->mu64[HEOM_OP_MU_PLUS] = upload_vec(hm.mu_plus, st);
+  m->mu64[HEOM_OP_MU_MINUS] = upload_vec(hm.mu_minus, st);
+  for (int dir = 0; dir < 2; ++dir) {
+    const heom::Neighbours& nb = dir == 0 ? hm.fwd : hm.adj;
+    m->nb_ptr[dir] = upload_vec(nb.ptr, st);
+    m->nb_idx[dir] = upload_vec(nb.idx, st);
+    std::vector<double> a(nb.aL.size() * 4);
+    for (size_t q = 0; q < nb.aL.size(); ++q) {
+      a[4 * q] = nb.aL[q].real();
+      a[4 * q + 1] = nb.aL[q].imag();
+      a[4 * q + 2] = nb.aR[q].real();
+      a[4 * q + 3] = nb.aR[q].imag();
+    }
+    m->nb_a64[dir] = upload_vec(a, st);
+    m->nb_a32[dir] = f32(a);
+    auto fill = [&](auto& op, const DevBuf& H, const DevBuf& v, const DevBuf& g, const DevBuf& na) {
+      using T = std::remove_const_t<std::remove_pointer_t<decltype(op.H)>>;
+      op.H = H.as<T>();
+      op.v = v.as<T>();
+      op.gamma = g.as<T>();
+      op.nb_ptr = m->nb_ptr[dir].as<int>();
+      op.nb_idx = m->nb_idx[dir].as<int>();
+      op.nb_a = na.as<T>();
+      for (int s = 0; s < 4; ++s) {
+        op.v_off[s] = v_off[s];
+        op.dims[s] = hm.dims[s];
+        op.strides[s] = hm.strides[s];
+      }
+      op.n_modes = hm.n_modes;
+      op.d = hm.d;
+      op.n_ado = hm.n_ado;
+    };
+    fill(m->ops64[dir], m->H64, m->v64, m->g64, m->nb_a64[dir]);
+    fill(m->ops32[dir], m->H32, m->v32, m->g32, m->nb_a32[dir]);
+  }
+  m->red_result = DevBuf(sizeof(double) * 4);
+  m->has_device = true;
+}
+
+// typed helpers ------------------------------------------------------------
+
+template <typename T>
+const heom::DevOps<T>& ops_of(const heom_model* m, bool adjoint);
+template <>
+const heom::DevOps<double>& ops_of<double>(const heom_model* m, bool adjoint) { return m->ops64[adjoint ? 1 : 0]; }
+template <>
+const heom::DevOps<float>& ops_of<float>(const heom_model* m, bool adjoint) { return m->ops32[adjoint ? 1 : 0]; }
+
+std::pair<hipEvent_t, hipEvent_t> next_event_pair(heom_model* m) {
+  if (m->events_used == m->events.size()) {
+    hipEvent_t a, b;
+    hip_check(hipEventCreate(&a), "event create");
+    hip_check(hipEventCreate(&b), "event create");
+    m->events.emplace_back(a, b);
+  }
+  return m->events[m->events_used++];
+}
+
+// One launch of the fused RHS / RK4-stage kernel (timed when enabled).
+template <typename T>
+void stage(heom_model* m, bool adjoint, const T* in, const T* y, T* out, double coef, int n_traj) {
+  const auto& op = ops_of<T>(m, adjoint);
+  if (m->timing) {
+    auto ev = next_event_pair(m);
+    hip_check(hipEventRecord(ev.first, m->stream), "event record");
+    heom::launch_rhs<T>(op, in, y, out, coef, n_traj, m->stream);
+    hip_check(hipEventRecord(ev.second, m->stream), "event record");
+    m->launches += 1;
+    m->ado_updates += static_cast<long long>(n_traj) * m->hm.n_ado;
+  } else {
+    heom::launch_rhs<T>(op, in, y, out, coef, n_traj, m->stream);
+  }
+}
+
+template <typename T>
+T* scratch(heom_model* m, int slot, long long elems) {
+  size_t bytes = static_cast<size_t>(elems) * sizeof(T);
+  if (m->scratch[slot].bytes < bytes) {
+    hip_check(hipStreamSynchronize(m->stream), "sync before scratch growth");
+    m->scratch[slot] = DevBuf();
+    m->scratch[slot] = DevBuf(bytes);
+  }
+  return m->scratch[slot].as<T>();
+}
+
+// n_steps RK4 steps in place on y (n_traj trajectories), with work buffers
+// w1, w2 of the same size:  y <- y + h L(y + h/2 L(y + h/3 L(y + h/4 L y))).
+template <typename T>
+void rk4_steps(heom_model* m, T* y, T* w1, T* w2, int n_traj, int n_steps, bool adjoint) {
+  const double h = m->hm.dt;
+  for (int s = 0; s < n_steps; ++s) {
+    stage<T>(m, adjoint, y, y, w1, h / 4.0, n_traj);
+    stage<T>(m, adjoint, w1, y, w2, h / 3.0, n_traj);
+    stage<T>(m, adjoint, w2, y, w1, h / 2.0, n_traj);
+    stage<T>(m, adjoint, w1, y, y, h, n_traj);
+  }
+}
+
+template <typename T>
+void rk4_steps_scratch(heom_model* m, T* y, int n_traj, int n_steps, bool adjoint) {
+  if (n_steps <= 0) return;
+  const long long elems = static_cast<long long>(n_traj) * m->traj_elems();
+  T* w1 = scratch<T>(m, 0, elems);
+  T* w2 = scratch<T>(m, 1, elems);
+  rk4_steps<T>(m, y, w1, w2, n_traj, n_steps, adjoint);
+}
+
+template <typename T>
+double absmax(heom_model* m, const T* x, long long n_mats) {
+  if (m->red_partial.bytes < static_cast<size_t>(n_mats) * sizeof(double)) {
+    hip_check(hipStreamSynchronize(m->stream), "sync");
+    m->red_partial = DevBuf();
+    m->red_partial = DevBuf(static_cast<size_t>(n_mats) * sizeof(double));
+  }
+  heom::launch_absmax<T>(x, m->hm.d, n_mats, m->red_partial.as<double>(), m->red_result.as<double>(),
+                         m->stream);
+  double r = 0.0;
+  hip_check(hipMemcpyAsync(&r, m->red_result.p, sizeof(double), hipMemcpyDeviceToHost, m->stream), "copy");
+  hip_check(hipStreamSynchronize(m->stream), "sync");
+  return r;
+}
+
+// L(x) into scratch slot 0, then max |.|
+template <typename T>
+double residual_of(heom_model* m, const T* x, int n_traj) {
+  const long long elems = static_cast<long long>(n_traj) * m->traj_elems();
+  T* w = scratch<T>(m, 0, elems);
+  heom::launch_rhs<T>(ops_of<T>(m, false), x, nullptr, w, 1.0, n_traj, m->stream);
+  return absmax<T>(m, w, static_cast<long long>(n_traj) * m->hm.n_ado);
+}
+
+template <typename T>
+void check_finite(heom_model* m, const T* x, int n_traj, const char* where) {
+  double r = absmax<T>(m, x, static_cast<long long>(n_traj) * m->hm.n_ado);
+  if (!std::isfinite(r))
+    throw HeomError(HEOM_ERR_UNSTABLE, std::string("non-finite hierarchy after ") + where +
+                                           " (time step beyond the RK4 stability region?)");
+}
+
+std::unique_ptr<heom_state> new_state(heom_model* m, int n_traj, int prec) {
+  auto s = std::make_unique<heom_state>();
+  s->model = m;
+  s->n_traj = n_traj;
+  s->precision = prec;
+  s->buf = DevBuf(static_cast<size_t>(s->n_elems()) * s->elem_size());
+  // zero fill
+  if (prec == HEOM_FP64)
+    heom::launch_set_ground<double>(s->buf.as<double>(), m->traj_elems(), 0, s->n_elems(), m->stream);
+  else
+    heom::launch_set_ground<float>(s->buf.as<float>(), m->traj_elems(), 0, s->n_elems(), m->stream);
+  return s;
+}
+
+// dst (precision of dst) <- D^x src (FP64 source), n matrices.
+template <typename T>
+void commute_from64(heom_model* m, int op, int transpose, const double* src, T* dst, long long n_mats,
+                    double* tmp64) {
+  if constexpr (std::is_same<T, double>::value) {
+    heom::launch_commutator<double>(m->mu64[op].as<double>(), transpose, src, dst, m->hm.d, n_mats, m->stream);
+  } else {
+    heom::launch_commutator<double>(m->mu64[op].as<double>(), transpose, src, tmp64, m->hm.d, n_mats,
+                                    m->stream);
+    heom::launch_convert<double, T>(tmp64, dst, n_mats * 2 * m->hm.d * m->hm.d, m->stream);
+  }
+}
+
+size_t free_device_bytes() {
+  size_t fr = 0, tot = 0;
+  hip_check(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
+  return fr;
+}
+
+// ------------------------------------------------------------- responses --
+
+template <typename T>
+void linear_response_impl(heom_model* m, const heom_state* rho_eq, int n, int sps, double* R_out) {
+  const long long te = m->traj_elems();
+  const int d = m->hm.d;
+  DevBuf X(static_cast<size_t>(te) * sizeof(T));
+  DevBuf tmp(static_cast<size_t>(te) * sizeof(double));
+  commute_from64<T>(m, HEOM_OP_MU, 0, rho_eq->buf.as<double>(), X.as<T>(), m->hm.n_ado, tmp.as<double>());
+  DevBuf out(static_cast<size_t>(n) * 2 * sizeof(double));
+  for (int k = 0; k < n; ++k) {
+    if (k) rk4_steps_scratch<T>(m, X.as<T>(), 1, sps, false);
+    heom::launch_trace<T>(m->mu64[HEOM_OP_MU].as<double>(), X.as<T>(), d, te, 1, out.as<double>() + 2 * k, 1,
+                          m->stream);
+  }
+  check_finite<T>(m, X.as<T>(), 1, "linear response");
+  std::vector<double> h(static_cast<size_t>(n) * 2);
+  hip_check(hipMemcpyAsync(h.data(), out.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, m->stream), "copy");
+  hip_check(hipStreamSynchronize(m->stream), "sync");
+  for (int k = 0; k < n; ++k) {  // R1 = i * tr(...)
+    R_out[2 * k] = -h[2 * k + 1];
+    R_out[2 * k + 1] = h[2 * k];
+  }
+}
+
+// Snapshots of the t1 trajectory: snap[j] = D2^x G(t1_j) D1^x rho_eq.
+template <typename T>
+void t1_snapshots(heom_model* m, const heom_state* rho_eq, int D1, int D2, int n1, int sps, T* snap) {
+  const long long te = m->traj_elems();
+  const long long n_mats = m->hm.n_ado;
+  DevBuf X(static_cast<size_t>(te) * sizeof(T));
+  DevBuf tmp(static_cast<size_t>(te) * sizeof(double));
+  commute_from64<T>(m, D1, 0, rho_eq->buf.as<double>(), X.as<T>(), n_mats, tmp.as<double>());
+  for (int j = 0; j < n1; ++j) {
+    if (j) rk4_steps_scratch<T>(m, X.as<T>(), 1, sps, false);
+    heom::launch_commutator<T>(m->mu64[D2].as<double>(), 0, X.as<T>(), snap + j * te, m->hm.d, n_mats,
+                               m->stream);
+  }
+  check_finite<T>(m, X.as<T>(), 1, "t1 scan");
+}
+
+int auto_batch(heom_model* m, int n_total, size_t elem, long long per_traj_buffers, size_t fixed_bytes,
+               int max_batch) {
+  if (max_batch > 0) return std::min(max_batch, n_total);
+  const size_t te_bytes = static_cast<size_t>(m->traj_elems()) * elem;
+  size_t fr = free_device_bytes();
+  size_t budget = fr > fixed_bytes + (size_t(2) << 30) ? fr - fixed_bytes - (size_t(2) << 30) : 0;
+  long long c = static_cast<long long>(budget / (te_bytes * per_traj_buffers));
+  if (c < 1) throw HeomError(HEOM_ERR_OOM, "not enough device memory for one trajectory batch");
+  return static_cast<int>(std::min<long long>(c, n_total));
+}
+
+template <typename T>
+void response_direct(heom_model* m, const heom_state* rho_eq, const heom_grid& g, int max_batch, double* Rdev) {
+  const long long te = m->traj_elems();
+  const int d = m->hm.d;
+  const int n1 = g.n1, n3 = g.n3, sps = g.steps_per_sample;
+  const size_t tb = static_cast<size_t>(te) * sizeof(T);
+  DevBuf snap(tb * n1);
+  const int C = auto_batch(m, n1, sizeof(T), 3, 0, max_batch);
+  DevBuf Z(tb * C), W1(tb * C), W2(tb * C);
+  const int pw_d[2][3] = {{HEOM_OP_MU_MINUS, HEOM_OP_MU_PLUS, HEOM_OP_MU_PLUS},
+                          {HEOM_OP_MU_PLUS, HEOM_OP_MU_MINUS, HEOM_OP_MU_PLUS}};
+  for (int P = 0; P < 2; ++P) {
+    t1_snapshots<T>(m, rho_eq, pw_d[P][0], pw_d[P][1], n1, sps, snap.as<T>());
+    for (int j0 = 0; j0 < n1; j0 += C) {
+      const int c = std::min(C, n1 - j0);
+      T* Y = snap.as<T>() + j0 * te;
+      int done = 0;
+      for (int i = 0; i < g.n_t2; ++i) {
+        rk4_steps<T>(m, Y, W1.as<T>(), W2.as<T>(), c, g.t2_steps[i] - done, false);
+        done = g.t2_steps[i];
+        heom::launch_commutator<T>(m->mu64[pw_d[P][2]].as<double>(), 0, Y, Z.as<T>(), d,
+                                   static_cast<long long>(c) * m->hm.n_ado, m->stream);
+        for (int k = 0; k < n3; ++k) {
+          if (k) rk4_steps<T>(m, Z.as<T>(), W1.as<T>(), W2.as<T>(), c, sps, false);
+          double* out = Rdev + 2 * ((((static_cast<long long>(i) * 2 + P) * n1 + j0) * n3) + k);
+          heom::launch_trace<T>(m->mu64[HEOM_OP_MU].as<double>(), Z.as<T>(), d, te, c, out, n3, m->stream);
+        }
+        check_finite<T>(m, Z.as<T>(), c, "t3 propagation");
+      }
+    }
+  }
+}
+
+template <typename T>
+void response_adjoint(heom_model* m, const heom_state* rho_eq, const heom_grid& g, int max_batch, double* Rdev) {
+  const long long te = m->traj_elems();
+  const int d = m->hm.d;
+  const int n1 = g.n1, n3 = g.n3, sps = g.steps_per_sample;
+  const size_t tb = static_cast<size_t>(te) * sizeof(T);
+  // detection functional: l_0 = mu^T (n = 0 ADO), propagated with L^T;
+  // Psi_k = (D3^x)^T l(t3_k), D3 = mu_plus for both pathways.
+  DevBuf Psi(tb * n3);
+  {
+    std::vector<double> h(static_cast<size_t>(te), 0.0);
+    for (int a = 0; a < d; ++a)
+      for (int c = 0; c < d; ++c) h[static_cast<size_t>(a) * d + c] = m->hm.mu[static_cast<size_t>(c) * d + a];
+    DevBuf l64 = upload_vec(h, m->stream);
+    DevBuf l(tb);
+    heom::launch_convert<double, T>(l64.as<double>(), l.as<T>(), te, m->stream);
+    for (int k = 0; k < n3; ++k) {
+      if (k) rk4_steps_scratch<T>(m, l.as<T>(), 1, sps, true);
+      heom::launch_commutator<T>(m->mu64[HEOM_OP_MU_PLUS].as<double>(), 1, l.as<T>(), Psi.as<T>() + k * te, d,
+                                 m->hm.n_ado, m->stream);
+    }
+    check_finite<T>(m, l.as<T>(), 1, "adjoint t3 scan");
+  }
+  DevBuf snap(tb * n1);
+  const int C = auto_batch(m, n1, sizeof(T), 2, 0, max_batch);
+  DevBuf W1(tb * C), W2(tb * C);
+  DevBuf work(heom::pair_work_doubles(C, n3, m->hm.n_ado, d) * sizeof(double));
+  const int pw_d[2][2] = {{HEOM_OP_MU_MINUS, HEOM_OP_MU_PLUS}, {HEOM_OP_MU_PLUS, HEOM_OP_MU_MINUS}};
+  for (int P = 0; P < 2; ++P) {
+    t1_snapshots<T>(m, rho_eq, pw_d[P][0], pw_d[P][1], n1, sps, snap.as<T>());
+    for (int j0 = 0; j0 < n1; j0 += C) {
+      const int c = std::min(C, n1 - j0);
+      T* Y = snap.as<T>() + j0 * te;
+      int done = 0;
+      for (int i = 0; i < g.n_t2; ++i) {
+        rk4_steps<T>(m, Y, W1.as<T>(), W2.as<T>(), c, g.t2_steps[i] - done, false);
+        done = g.t2_steps[i];
+        double* out = Rdev + 2 * (((static_cast<long long>(i) * 2 + P) * n1 + j0) * n3);
+        // R = i^3 <Psi_k, Y_j> = -i <.,.>
+        heom::launch_pairing<T>(Y, c, Psi.as<T>(), n3, m->hm.n_ado, d, 0.0, -1.0, work.as<double>(), out,
+                                m->stream);
+      }
+      check_finite<T>(m, Y, c, "t2 propagation");
+    }
+  }
+}
+
+}  // namespace
+
+// ============================================================== C ABI =====
+
+extern "C" {
+
+const char* heom_last_error(void) { return g_last_error.c_str(); }
+
+int heom_set_allocator(heom_alloc_fn alloc, heom_free_fn release, void* ctx) {
+  return guarded([&] {
+    if ((alloc == nullptr) != (release == nullptr))
+      throw HeomError(HEOM_ERR_PARAM, "alloc and free hooks must be given together");
+    g_alloc = alloc;
+    g_free = release;
+    g_alloc_ctx = ctx;
+  });
+}
+
+int heom_device_query(int* cu_count, int* lds_bytes, char* name_out, int name_len) {
+  return guarded([&] {
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    hipDeviceProp_t prop;
+    hip_check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+    if (cu_count) *cu_count = prop.multiProcessorCount;
+    if (lds_bytes) *lds_bytes = static_cast<int>(prop.sharedMemPerBlock);
+    if (name_out && name_len > 0) {
+      std::snprintf(name_out, static_cast<size_t>(name_len), "%s (%s)", prop.name, prop.gcnArchName);
+    }
+  });
+}
+
+int heom_model_build_host(const heom_params* params, heom_model** out) {
+  return guarded([&] {
+    if (!out) throw HeomError(HEOM_ERR_PARAM, "null output pointer");
+    *out = nullptr;
+    heom_params p = copy_check(params);
+    auto m = std::make_unique<heom_model>();
+    m->hm = heom::build_host_model(p);
+    *out = m.release();
+  });
+}
+
+int heom_model_build(const heom_params* params, void* hip_stream, heom_model** out) {
+  return guarded([&] {
+    if (!out) throw HeomError(HEOM_ERR_PARAM, "null output pointer");
+    *out = nullptr;
+    heom_params p = copy_check(params);
+    auto m = std::make_unique<heom_model>();
+    m->hm = heom::build_host_model(p);
+    hip_check(hipGetDevice(&m->device), "hipGetDevice");
+    hipDeviceProp_t prop;
+    hip_check(hipGetDeviceProperties(&prop, m->device), "hipGetDeviceProperties");
+    m->lds_limit = static_cast<int>(prop.sharedMemPerBlock);
+    m->stream = static_cast<hipStream_t>(hip_stream);
+    const long long need_lds = static_cast<long long>(m->hm.d) * m->hm.d * sizeof(double);
+    if (need_lds > m->lds_limit)
+      throw HeomError(HEOM_ERR_PARAM, "product dimension too large for the FP64 kernel's LDS staging");
+    upload_model(m.get());
+    *out = m.release();
+  });
+}
+
+void heom_model_free(heom_model* model) {
+  if (!model) return;
+  if (model->has_device) (void)hipStreamSynchronize(model->stream);
+  delete model;
+}
+
+int heom_model_info(const heom_model* m, heom_info* out) {
+  return guarded([&] {
+    if (!m || !out) throw HeomError(HEOM_ERR_PARAM, "null argument");
+    out->d = m->hm.d;
+    out->n_ado = m->hm.n_ado;
+    out->n_terms = m->hm.n_terms;
+    out->n_modes = m->hm.n_modes;
+    for (int s = 0; s < 4; ++s) out->dims[s] = s < m->hm.n_modes ? m->hm.dims[s] : 1;
+    out->depth = m->hm.depth;
+    out->dt = m->hm.dt;
+  });
+}
+
+int heom_model_operators(const heom_model* m, double* H, double* mu, double* mu_plus, double* mu_minus,
+                         double* v, double* nu, double* c, int* ado_n, int* term_mode) {
+  return guarded([&] {
+    if (!m) throw HeomError(HEOM_ERR_PARAM, "null model");
+    const auto& hm = m->hm;
+    auto cp = [](double* dst, const std::vector<double>& src) {
+      if (dst) std::memcpy(dst, src.data(), src.size() * sizeof(double));
+    };
+    cp(H, hm.H);
+    cp(mu, hm.mu);
+    cp(mu_plus, hm.mu_plus);
+    cp(mu_minus, hm.mu_minus);
+    if (v) {
+      size_t off = 0;
+      for (const auto& vs : hm.v) {
+        std::memcpy(v + off, vs.data(), vs.size() * sizeof(double));
+        off += vs.size();
+      }
+    }
+    cp(nu, hm.nu);
+    if (c)
+      for (int j = 0; j < hm.n_terms; ++j) {
+        c[2 * j] = hm.c[j].real();
+        c[2 * j + 1] = hm.c[j].imag();
+      }
+    if (ado_n) std::memcpy(ado_n, hm.ado_n.data(), hm.ado_n.size() * sizeof(int));
+    if (term_mode) std::memcpy(term_mode, hm.term_mode.data(), hm.term_mode.size() * sizeof(int));
+  });
+}
+
+int heom_state_create(heom_model* m, int n_traj, int precision, heom_state** out) {
+  return guarded([&] {
+    require_device(m);
+    if (!out) throw HeomError(HEOM_ERR_PARAM, "null output pointer");
+    *out = nullptr;
+    if (n_traj < 1) throw HeomError(HEOM_ERR_PARAM, "n_traj must be >= 1");
+    if (precision != HEOM_FP64 && precision != HEOM_FP32) throw HeomError(HEOM_ERR_PARAM, "bad precision");
+    auto s = new_state(m, n_traj, precision);
+    hip_check(hipStreamSynchronize(m->stream), "sync");
+    *out = s.release();
+  });
+}
+
+void heom_state_free(heom_state* s) {
+  if (!s) return;
+  if (s->model && s->model->has_device) (void)hipStreamSynchronize(s->model->stream);
+  delete s;
+}
+
+int heom_state_shape(const heom_state* s, int* n_traj, int* precision) {
+  return guarded([&] {
+    if (!s) throw HeomError(HEOM_ERR_PARAM, "null state");
+    if (n_traj) *n_traj = s->n_traj;
+    if (precision) *precision = s->precision;
+  });
+}
+
+int heom_state_upload_range(heom_state* s, int first, int count, const double* host) {
+  return guarded([&] {
+    if (!s || !host) throw HeomError(HEOM_ERR_PARAM, "null argument");
+    if (first < 0 || count < 0 || first + count > s->n_traj) throw HeomError(HEOM_ERR_PARAM, "bad trajectory range");
+    heom_model* m = s->model;
+    const int d = m->hm.d;
+    const long long dd = static_cast<long long>(d) * d;
+    const long long n_mats = static_cast<long long>(count) * m->hm.n_ado;
+    const long long off = static_cast<long long>(first) * m->traj_elems();
+    auto go = [&](auto* tag) {
+      using T = std::remove_pointer_t<decltype(tag)>;
+      std::vector<T> t(static_cast<size_t>(n_mats * 2 * dd));
+      for (long long q = 0; q < n_mats; ++q)
+        for (long long e = 0; e < dd; ++e) {
+          t[q * 2 * dd + e] = static_cast<T>(host[2 * (q * dd + e)]);
+          t[q * 2 * dd + dd + e] = static_cast<T>(host[2 * (q * dd + e) + 1]);
+        }
+      hip_check(hipMemcpyAsync(s->buf.as<T>() + off, t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice,
+                               m->stream), "upload");
+      hip_check(hipStreamSynchronize(m->stream), "sync");
+    };
+    if (s->precision == HEOM_FP64) go(static_cast<double*>(nullptr));
+    else go(static_cast<float*>(nullptr));
+  });
+}
+
+int heom_state_download_range(const heom_state* s, int first, int count, double* host) {
+  return guarded([&] {
+    if (!s || !host) throw HeomError(HEOM_ERR_PARAM, "null argument");
+    if (first < 0 || count < 0 || first + count > s->n_traj) throw HeomError(HEOM_ERR_PARAM, "bad trajectory range");
+    heom_model* m = s->model;
+    const int d = m->hm.d;
+    const long long dd = static_cast<long long>(d) * d;
+    const long long n_mats = static_cast<long long>(count) * m->hm.n_ado;
+    const long long off = static_cast<long long>(first) * m->traj_elems();
+    auto go = [&](auto* tag) {
+      using T = std::remove_pointer_t<decltype(tag)>;
+      std::vector<T> t(static_cast<size_t>(n_mats * 2 * dd));
+      hip_check(hipMemcpyAsync(t.data(), s->buf.as<T>() + off, t.size() * sizeof(T), hipMemcpyDeviceToHost,
+                               m->stream), "download");
+      hip_check(hipStreamSynchronize(m->stream), "sync");
+      for (long long q = 0; q < n_mats; ++q)
+        for (long long e = 0; e < dd; ++e) {
+          host[2 * (q * dd + e)] = static_cast<double>(t[q * 2 * dd + e]);
+          host[2 * (q * dd + e) + 1] = static_cast<double>(t[q * 2 * dd + dd + e]);
+        }
+    };
+    if (s->precision == HEOM_FP64) go(static_cast<double*>(nullptr));
+    else go(static_cast<float*>(nullptr));
+  });
+}
+
+int heom_state_upload(heom_state* s, const double* host) {
+  if (!s) {
+    g_last_error = "null state";
+    return HEOM_ERR_PARAM;
+  }
+  return heom_state_upload_range(s, 0, s->n_traj, host);
+}
+
+int heom_state_download(const heom_state* s, double* host) {
+  if (!s) {
+    g_last_error = "null state";
+    return HEOM_ERR_PARAM;
+  }
+  return heom_state_download_range(s, 0, s->n_traj, host);
+}
+
+int heom_state_set_ground(heom_state* s) {
+  return guarded([&] {
+    if (!s) throw HeomError(HEOM_ERR_PARAM, "null state");
+    heom_model* m = s->model;
+    if (s->precision == HEOM_FP64)
+      heom::launch_set_ground<double>(s->buf.as<double>(), m->traj_elems(), s->n_traj, s->n_elems(), m->stream);
+    else
+      heom::launch_set_ground<float>(s->buf.as<float>(), m->traj_elems(), s->n_traj, s->n_elems(), m->stream);
+    hip_check(hipStreamSynchronize(m->stream), "sync");
+  });
+}
+
+int heom_state_copy(heom_state* dst, const heom_state* src) {
+  return guarded([&] {
+    if (!dst || !src) throw HeomError(HEOM_ERR_PARAM, "null state");
+    if (dst->model != src->model) throw HeomError(HEOM_ERR_STATE, "states of different models");
+    if (dst->n_traj != src->n_traj) throw HeomError(HEOM_ERR_STATE, "trajectory counts differ");
+    heom_model* m = dst->model;
+    const long long n = src->n_elems();
+    if (src->precision == HEOM_FP64 && dst->precision == HEOM_FP64)
+      heom::launch_convert<double, double>(src->buf.as<double>(), dst->buf.as<double>(), n, m->stream);
+    else if (src->precision == HEOM_FP64)
+      heom::launch_convert<double, float>(src->buf.as<double>(), dst->buf.as<float>(), n, m->stream);
+    else if (dst->precision == HEOM_FP64)
+      heom::launch_convert<float, double>(src->buf.as<float>(), dst->buf.as<double>(), n, m->stream);
+    else
+      heom::launch_convert<float, float>(src->buf.as<float>(), dst->buf.as<float>(), n, m->stream);
+    hip_check(hipStreamSynchronize(m->stream), "sync");
+  });
+}
+
+int heom_rhs(heom_model* m, const heom_state* in, heom_state* out, int adjoint) {
+  return guarded([&] {
+    require_device(m);
+    require_state(m, in);
+    require_state(m, out);
+    if (in == out) throw HeomError(HEOM_ERR_PARAM, "in and out must differ");
+    if (in->n_traj != out->n_traj || in->precision != out->precision)
+      throw HeomError(HEOM_ERR_STATE, "in/out shapes differ");
+    if (in->precision == HEOM_FP64)
+      heom::launch_rhs<double>(ops_of<double>(m, adjoint != 0), in->buf.as<double>(), nullptr,
+                               out->buf.as<double>(), 1.0, in->n_traj, m->stream);
+    else
+      heom::launch_rhs<float>(ops_of<float>(m, adjoint != 0), in->buf.as<float>(), nullptr, out->buf.as<float>(),
+                              1.0, in->n_traj, m->stream);
+    hip_check(hipStreamSynchronize(m->stream), "sync");
+  });
+}
+
+int heom_propagate(heom_model* m, heom_state* s, int n_steps, int adjoint) {
+  return guarded([&] {
+    require_device(m);
+    require_state(m, s);
+    if (n_steps < 0) throw HeomError(HEOM_ERR_PARAM, "n_steps must be >= 0");
+    if (s->precision == HEOM_FP64) {
+      rk4_steps_scratch<double>(m, s->buf.as<double>(), s->n_traj, n_steps, adjoint != 0);
+      check_finite<double>(m, s->buf.as<double>(), s->n_traj, "propagation");
+    } else {
+      rk4_steps_scratch<float>(m, s->buf.as<float>(), s->n_traj, n_steps, adjoint != 0);
+      check_finite<float>(m, s->buf.as<float>(), s->n_traj, "propagation");
+    }
+  });
+}
+
+int heom_apply_dipole(heom_model* m, heom_state* s, int op, int transpose) {
+  return guarded([&] {
+    require_device(m);
+    require_state(m, s);
+    if (op < 0 || op > 2) throw HeomError(HEOM_ERR_PARAM, "bad operator");
+    const long long n_mats = static_cast<long long>(s->n_traj) * m->hm.n_ado;
+    const long long n = s->n_elems();
+    if (s->precision == HEOM_FP64) {
+      double* w = scratch<double>(m, 0, n);
+      heom::launch_commutator<double>(m->mu64[op].as<double>(), transpose, s->buf.as<double>(), w, m->hm.d,
+                                      n_mats, m->stream);
+      heom::launch_convert<double, double>(w, s->buf.as<double>(), n, m->stream);
+    } else {
+      float* w = scratch<float>(m, 0, n);
+      heom::launch_commutator<float>(m->mu64[op].as<double>(), transpose, s->buf.as<float>(), w, m->hm.d, n_mats,
+                                     m->stream);
+      heom::launch_convert<float, float>(w, s->buf.as<float>(), n, m->stream);
+    }
+    hip_check(hipStreamSynchronize(m->stream), "sync");
+  });
+}
+
+int heom_trace(heom_model* m, const heom_state* s, int op, double* out) {
+  return guarded([&] {
+    require_device(m);
+    require_state(m, s);
+    if (op < 0 || op > 2 || !out) throw HeomError(HEOM_ERR_PARAM, "bad argument");
+    DevBuf o(static_cast<size_t>(s->n_traj) * 2 * sizeof(double));
+    if (s->precision == HEOM_FP64)
+      heom::launch_trace<double>(m->mu64[op].as<double>(), s->buf.as<double>(), m->hm.d, m->traj_elems(),
+                                 s->n_traj, o.as<double>(), 1, m->stream);
+    else
+      heom::launch_trace<float>(m->mu64[op].as<double>(), s->buf.as<float>(), m->hm.d, m->traj_elems(), s->n_traj,
+                                o.as<double>(), 1, m->stream);
+    hip_check(hipMemcpyAsync(out, o.p, o.bytes, hipMemcpyDeviceToHost, m->stream), "copy");
+    hip_check(hipStreamSynchronize(m->stream), "sync");
+  });
+}
+
+int heom_residual(heom_model* m, const heom_state* s, double* out) {
+  return guarded([&] {
+    require_device(m);
+    require_state(m, s);
+    if (!out) throw HeomError(HEOM_ERR_PARAM, "null output");
+    *out = s->precision == HEOM_FP64 ? residual_of<double>(m, s->buf.as<double>(), s->n_traj)
+                                     : residual_of<float>(m, s->buf.as<float>(), s->n_traj);
+  });
+}
+
+int heom_equilibrate(heom_model* m, double tol, int check_every, int min_steps, int max_steps,
+                     int require_convergence, heom_state** rho_eq_out, int* steps_out, double* residual_out) {
+  int conv_fail = 0;
+  int rc = guarded([&] {
+    require_device(m);
+    if (!rho_eq_out) throw HeomError(HEOM_ERR_PARAM, "null output pointer");
+    *rho_eq_out = nullptr;
+    if (check_every < 1 || max_steps < 0 || min_steps < 0) throw HeomError(HEOM_ERR_PARAM, "bad step counts");
+    auto s = new_state(m, 1, HEOM_FP64);
+    heom::launch_set_ground<double>(s->buf.as<double>(), m->traj_elems(), 1, s->n_elems(), m->stream);
+    double* y = s->buf.as<double>();
+    const long long te = m->traj_elems();
+    DevBuf w1(static_cast<size_t>(te) * sizeof(double)), w2(static_cast<size_t>(te) * sizeof(double));
+    int steps = 0;
+    double res = -1.0;
+    while (steps < max_steps) {
+      const int k = std::min(check_every, max_steps - steps);
+      rk4_steps<double>(m, y, w1.as<double>(), w2.as<double>(), 1, k, false);
+      steps += k;
+      res = -1.0;
+      if (steps >= min_steps) {
+        res = residual_of<double>(m, y, 1);
+        if (!std::isfinite(res)) throw HeomError(HEOM_ERR_UNSTABLE, "non-finite hierarchy during equilibration");
+        if (res <= tol) break;
+      }
+    }
+    if (res < 0.0) res = residual_of<double>(m, y, 1);
+    if (steps_out) *steps_out = steps;
+    if (residual_out) *residual_out = res;
+    if (require_convergence && res > tol) conv_fail = 1;
+    *rho_eq_out = s.release();
+  });
+  if (rc == HEOM_OK && conv_fail) {
+    g_last_error = "equilibration residual above tolerance at max_steps";
+    return HEOM_ERR_NOCONV;
+  }
+  return rc;
+}
+
+int heom_linear_response(heom_model* m, const heom_state* rho_eq, int n, int sps, int precision, double* R_out) {
+  return guarded([&] {
+    require_device(m);
+    require_state(m, rho_eq);
+    if (rho_eq->precision != HEOM_FP64 || rho_eq->n_traj != 1)
+      throw HeomError(HEOM_ERR_STATE, "rho_eq must be an FP64 state with one trajectory");
+    if (n < 1 || sps < 1 || !R_out) throw HeomError(HEOM_ERR_PARAM, "bad grid");
+    if (precision == HEOM_FP64) linear_response_impl<double>(m, rho_eq, n, sps, R_out);
+    else if (precision == HEOM_FP32) linear_response_impl<float>(m, rho_eq, n, sps, R_out);
+    else throw HeomError(HEOM_ERR_PARAM, "bad precision");
+  });
+}
+
+int heom_response_2d(heom_model* m, const heom_state* rho_eq, const heom_grid* grid, int precision, int method,
+                     int max_batch, double* R_out) {
+  return guarded([&] {
+    require_device(m);
+    require_state(m, rho_eq);
+    if (rho_eq->precision != HEOM_FP64 || rho_eq->n_traj != 1)
+      throw HeomError(HEOM_ERR_STATE, "rho_eq must be an FP64 state with one trajectory");
+    if (!grid || !R_out) throw HeomError(HEOM_ERR_PARAM, "null argument");
+    const heom_grid& g = *grid;
+    if (g.n1 < 1 || g.n3 < 1 || g.steps_per_sample < 1 || g.n_t2 < 1 || !g.t2_steps)
+      throw HeomError(HEOM_ERR_PARAM, "bad grid");
+    for (int i = 0; i < g.n_t2; ++i)
+      if (g.t2_steps[i] < 0 || (i && g.t2_steps[i] < g.t2_steps[i - 1]))
+        throw HeomError(HEOM_ERR_PARAM, "t2_steps must be non-negative and non-decreasing");
+    if (method != HEOM_RESP_DIRECT && method != HEOM_RESP_ADJOINT) throw HeomError(HEOM_ERR_PARAM, "bad method");
+    const size_t n_out = static_cast<size_t>(g.n_t2) * 2 * g.n1 * g.n3 * 2;
+    DevBuf Rdev(n_out * sizeof(double));
+    if (precision == HEOM_FP64) {
+      if (method == HEOM_RESP_DIRECT) response_direct<double>(m, rho_eq, g, max_batch, Rdev.as<double>());
+      else response_adjoint<double>(m, rho_eq, g, max_batch, Rdev.as<double>());
+    } else if (precision == HEOM_FP32) {
+      if (method == HEOM_RESP_DIRECT) response_direct<float>(m, rho_eq, g, max_batch, Rdev.as<double>());
+      else response_adjoint<float>(m, rho_eq, g, max_batch, Rdev.as<double>());
+    } else {
+      throw HeomError(HEOM_ERR_PARAM, "bad precision");
+    }
+    std::vector<double> h(n_out);
+    hip_check(hipMemcpyAsync(h.data(), Rdev.p, n_out * sizeof(double), hipMemcpyDeviceToHost, m->stream), "copy");
+    hip_check(hipStreamSynchronize(m->stream), "sync");
+    if (method == HEOM_RESP_DIRECT) {
+      // R = i^3 tr(...) = -i tr(...)
+      for (size_t q = 0; q < n_out / 2; ++q) {
+        R_out[2 * q] = h[2 * q + 1];
+        R_out[2 * q + 1] = -h[2 * q];
+      }
+    } else {
+      std::memcpy(R_out, h.data(), n_out * sizeof(double));
+    }
+  });
+}
+
+int heom_spectrum_2d(const double* R_I, const double* R_II, int n1, int n3, double dt_s, double* S_out) {
+  return guarded([&] {
+    if (!R_I || !R_II || !S_out || n1 < 1 || n3 < 1 || !(dt_s > 0.0))
+      throw HeomError(HEOM_ERR_PARAM, "bad argument");
+    const size_t nr = static_cast<size_t>(n1) * n3 * 2;
+    DevBuf dI(nr * sizeof(double)), dII(nr * sizeof(double));
+    DevBuf work(static_cast<size_t>(4) * n3 * n1 * 2 * sizeof(double));
+    DevBuf S(static_cast<size_t>(4) * n3 * n1 * sizeof(double));
+    hip_check(hipMemcpy(dI.p, R_I, nr * sizeof(double), hipMemcpyHostToDevice), "upload");
+    hip_check(hipMemcpy(dII.p, R_II, nr * sizeof(double), hipMemcpyHostToDevice), "upload");
+    heom::launch_spectrum(dI.as<double>(), dII.as<double>(), n1, n3, dt_s, work.as<double>(), S.as<double>(),
+                          nullptr);
+    hip_check(hipMemcpy(S_out, S.p, S.bytes, hipMemcpyDeviceToHost), "download");
+  });
+}
+
+int heom_timing_enable(heom_model* m, int enable) {
+  return guarded([&] {
+    require_device(m);
+    m->timing = enable != 0;
+  });
+}
+
+int heom_timing_read(heom_model* m, double* total_ms, long long* launches, long long* ado_updates) {
+  return guarded([&] {
+    require_device(m);
+    hip_check(hipStreamSynchronize(m->stream), "sync");
+    double tot = 0.0;
+    for (size_t i = 0; i < m->events_used; ++i) {
+      float ms = 0.0f;
+      hip_check(hipEventElapsedTime(&ms, m->events[i].first, m->events[i].second), "event elapsed");
+      tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = m->launches;
+    if (ado_updates) *ado_updates = m->ado_updates;
+    m->events_used = 0;
+    m->launches = 0;
+    m->ado_updates = 0;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+// Device-side data of one model and the launch wrappers of the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace heom {
+
+// Operators and hierarchy tables of a model on the device, in precision T.
+// The neighbour coefficients are stored as 4 values per entry:
+// (aL.re, aL.im, aR.re, aR.im).
+template <typename T>
+struct DevOps {
+  const T* H;          // d x d
+  const T* v;          // per mode dims[s]^2, packed
+  const T* gamma;      // per ADO: sum_j n_j nu_j
+  const int* nb_ptr;   // n_ado * n_modes + 1
+  const int* nb_idx;
+  const T* nb_a;
+  int v_off[4];
+  int dims[4];
+  int strides[4];
+  int n_modes;
+  int d;
+  int n_ado;
+};
+
+// out = L(in)                      (y == nullptr)
+// out = y + coef * L(in)           (y != nullptr; out may alias y)
+// for n_traj trajectories stored back to back ([traj][ado][re|im][d][d]).
+template <typename T>
+void launch_rhs(const DevOps<T>& op, const T* in, const T* y, T* out, double coef, int n_traj,
+                hipStream_t stream);
+
+// dst = D^x src (or (D^T)^x src) on every ADO, FP64 arithmetic.
+template <typename T>
+void launch_commutator(const double* D, int transpose, const T* src, T* dst, int d,
+                       long long n_mats, hipStream_t stream);
+
+// out[b * out_stride] = tr(A rho_{b, n=0}) (complex, FP64; out_stride in
+// complex units), rho_b at stride traj_stride elements.
+template <typename T>
+void launch_trace(const double* A, const T* state, int d, long long traj_stride, int n_traj,
+                  double* out, long long out_stride, hipStream_t stream);
+
+// Largest |z| over n_mats complex d x d matrices (NaN counts as +inf).
+// partial must hold n_mats doubles; result written to *result (device).
+template <typename T>
+void launch_absmax(const T* x, int d, long long n_mats, double* partial, double* result,
+                   hipStream_t stream);
+
+// dst (precision D) <- src (precision S), n elements.
+template <typename S, typename D>
+void launch_convert(const S* src, D* dst, long long n, hipStream_t stream);
+
+// x <- 0 then x[traj][ado 0][re][0][0] = 1.
+template <typename T>
+void launch_set_ground(T* x, long long traj_stride, int n_traj, long long n_total,
+                       hipStream_t stream);
+
+// Bilinear pairings R[j][k] = factor * sum_e P_k[e] Y_j[e] (complex, FP64
+// accumulation) between n1 hierarchies Y and n3 hierarchies P, each of
+// n_ado complex d x d matrices in planar layout.  out: [n1][n3] complex
+// (interleaved doubles, device).  work must hold
+// pair_work_doubles(n1, n3, n_ado, d) doubles.
+size_t pair_work_doubles(int n1, int n3, int n_ado, int d);
+template <typename T>
+void launch_pairing(const T* Y, int n1, const T* P, int n3, int n_ado, int d, double fac_re,
+                    double fac_im, double* work, double* out, hipStream_t stream);
+
+// 2D correlation spectrum from R_I, R_II ([n1][n3] complex, device) into
+// S ([2 n3][2 n1], device).  work must hold 2 * 2 * n3 * n1 * 2 doubles.
+void launch_spectrum(const double* RI, const double* RII, int n1, int n3, double dt_s,
+                     double* work, double* S, hipStream_t stream);
+
+}  // namespace heom

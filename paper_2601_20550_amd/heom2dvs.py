@@ -1,0 +1,399 @@
+"""Python binding of libheom2dvs.so (ctypes; argument marshalling only).
+
+Every computation runs in the HIP library.  The functions carry the names of
+the C entry points declared in include/heom2dvs.h; PyTorch, when present,
+supplies the HIP stream (torch.cuda.current_stream()) and optionally its
+caching allocator for device memory.
+
+Host arrays are numpy complex128 of shape (n_traj, n_ado, d, d).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libheom2dvs.so")
+
+HEOM_OK = 0
+HEOM_ERR_PARAM = -1
+HEOM_ERR_OOM = -2
+HEOM_ERR_UNSTABLE = -3
+HEOM_ERR_NOCONV = -4
+HEOM_ERR_HIP = -5
+HEOM_ERR_STATE = -6
+
+HEOM_FP64, HEOM_FP32 = 0, 1
+HEOM_PADE, HEOM_MATSUBARA = 0, 1
+HEOM_OP_MU, HEOM_OP_MU_PLUS, HEOM_OP_MU_MINUS = 0, 1, 2
+HEOM_RESP_DIRECT, HEOM_RESP_ADJOINT = 0, 1
+
+_PREC = {"fp64": HEOM_FP64, "fp32": HEOM_FP32, HEOM_FP64: HEOM_FP64, HEOM_FP32: HEOM_FP32}
+_OPS = {"mu": HEOM_OP_MU, "mu_plus": HEOM_OP_MU_PLUS, "mu_minus": HEOM_OP_MU_MINUS}
+_METHOD = {"direct": HEOM_RESP_DIRECT, "adjoint": HEOM_RESP_ADJOINT,
+           HEOM_RESP_DIRECT: HEOM_RESP_DIRECT, HEOM_RESP_ADJOINT: HEOM_RESP_ADJOINT}
+
+
+class HeomError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class heom_mode(C.Structure):
+    _fields_ = [(n, C.c_double) for n in
+                ("omega", "g3", "g4", "V1", "V2", "zeta", "gamma", "mu1", "mu2")] + \
+               [("n_basis", C.c_int), ("n_keep", C.c_int), ("K", C.c_int)]
+
+
+class heom_coupling(C.Structure):
+    _fields_ = [("s", C.c_int), ("t", C.c_int), ("g_st", C.c_double), ("g_s2t", C.c_double),
+                ("g_st2", C.c_double), ("mu_st", C.c_double)]
+
+
+class heom_params(C.Structure):
+    _fields_ = [("n_modes", C.c_int), ("modes", C.POINTER(heom_mode)),
+                ("n_couplings", C.c_int), ("couplings", C.POINTER(heom_coupling)),
+                ("beta", C.c_double), ("depth", C.c_int), ("decomp", C.c_int),
+                ("dt", C.c_double)]
+
+
+class heom_info(C.Structure):
+    _fields_ = [("d", C.c_int), ("n_ado", C.c_int), ("n_terms", C.c_int), ("n_modes", C.c_int),
+                ("dims", C.c_int * 4), ("depth", C.c_int), ("dt", C.c_double)]
+
+
+class heom_grid(C.Structure):
+    _fields_ = [("n1", C.c_int), ("n3", C.c_int), ("steps_per_sample", C.c_int),
+                ("n_t2", C.c_int), ("t2_steps", C.POINTER(C.c_int))]
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "heom_last_error": (C.c_char_p, []),
+    "heom_set_allocator": (C.c_int, [_ALLOC_FN, _FREE_FN, C.c_void_p]),
+    "heom_device_query": (C.c_int, [C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_char_p, C.c_int]),
+    "heom_model_build": (C.c_int, [C.POINTER(heom_params), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "heom_model_build_host": (C.c_int, [C.POINTER(heom_params), C.POINTER(C.c_void_p)]),
+    "heom_model_free": (None, [C.c_void_p]),
+    "heom_model_info": (C.c_int, [C.c_void_p, C.POINTER(heom_info)]),
+    "heom_model_operators": (C.c_int, [C.c_void_p] + [C.c_void_p] * 9),
+    "heom_state_create": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_void_p)]),
+    "heom_state_free": (None, [C.c_void_p]),
+    "heom_state_shape": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "heom_state_upload": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "heom_state_download": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "heom_state_upload_range": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
+    "heom_state_download_range": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
+    "heom_state_set_ground": (C.c_int, [C.c_void_p]),
+    "heom_state_copy": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "heom_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "heom_propagate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int]),
+    "heom_apply_dipole": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int]),
+    "heom_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "heom_residual": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "heom_equilibrate": (C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int,
+                                   C.POINTER(C.c_void_p), C.POINTER(C.c_int),
+                                   C.POINTER(C.c_double)]),
+    "heom_linear_response": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int,
+                                       C.c_void_p]),
+    "heom_response_2d": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(heom_grid), C.c_int,
+                                   C.c_int, C.c_int, C.c_void_p]),
+    "heom_spectrum_2d": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_double,
+                                   C.c_void_p]),
+    "heom_timing_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "heom_timing_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
+                                   C.POINTER(C.c_longlong)]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libheom2dvs.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with "
+                          "`python -m paper_2601_20550_amd.build` (there is no CPU fallback)")
+    lib = C.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(rc):
+    if rc != HEOM_OK:
+        msg = _lib.heom_last_error()
+        raise HeomError(rc, msg.decode() if msg else "")
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data)
+
+
+def _params_struct(params):
+    modes = params["modes"]
+    arr = (heom_mode * len(modes))()
+    for i, m in enumerate(modes):
+        for k in ("omega", "g3", "g4", "V1", "V2", "zeta", "gamma", "mu1", "mu2"):
+            setattr(arr[i], k, float(m.get(k, 0.0)))
+        arr[i].n_basis = int(m["n_basis"])
+        arr[i].n_keep = int(m["n_keep"])
+        arr[i].K = int(m["K"])
+    cps = params.get("couplings", [])
+    carr = (heom_coupling * max(1, len(cps)))()
+    for i, c in enumerate(cps):
+        carr[i].s, carr[i].t = int(c["s"]), int(c["t"])
+        for k in ("g_st", "g_s2t", "g_st2", "mu_st"):
+            setattr(carr[i], k, float(c.get(k, 0.0)))
+    p = heom_params()
+    p.n_modes = len(modes)
+    p.modes = arr
+    p.n_couplings = len(cps)
+    p.couplings = carr
+    p.beta = float(params["beta"])
+    p.depth = int(params["depth"])
+    p.decomp = HEOM_MATSUBARA if params.get("decomp", "pade") == "matsubara" else HEOM_PADE
+    p.dt = float(params["dt"])
+    return p, (arr, carr)
+
+
+def _torch_stream_handle():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except ImportError:
+        pass
+    return C.c_void_p(0)
+
+
+_alloc_keepalive = []
+
+
+def heom_set_allocator_torch():
+    """Route device allocations through torch's caching allocator."""
+    import torch
+    lib = load_library()
+    dev = torch.cuda.current_device()
+
+    def _alloc(nbytes, ctx):
+        return torch.cuda.caching_allocator_alloc(int(nbytes), dev)
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    fa, ff = _ALLOC_FN(_alloc), _FREE_FN(_free)
+    _alloc_keepalive[:] = [fa, ff]
+    _check(lib.heom_set_allocator(fa, ff, None))
+
+
+def heom_device_query():
+    lib = load_library()
+    cu, lds = C.c_int(), C.c_int()
+    name = C.create_string_buffer(256)
+    _check(lib.heom_device_query(C.byref(cu), C.byref(lds), name, 256))
+    return {"cu_count": cu.value, "lds_bytes": lds.value, "name": name.value.decode()}
+
+
+class Model:
+    """A built model (host operators + device tables)."""
+
+    def __init__(self, params, stream=None, device=True):
+        lib = load_library()
+        self.params = params
+        p, keep = _params_struct(params)
+        h = C.c_void_p()
+        if device:
+            s = _torch_stream_handle() if stream is None else C.c_void_p(stream)
+            _check(lib.heom_model_build(C.byref(p), s, C.byref(h)))
+        else:
+            _check(lib.heom_model_build_host(C.byref(p), C.byref(h)))
+        self.handle = h
+        info = heom_info()
+        _check(lib.heom_model_info(h, C.byref(info)))
+        self.d, self.n_ado, self.n_terms = info.d, info.n_ado, info.n_terms
+        self.n_modes = info.n_modes
+        self.dims = tuple(info.dims[:info.n_modes])
+        self.depth, self.dt = info.depth, info.dt
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.heom_model_free(self.handle)
+            self.handle = None
+
+    def operators(self):
+        d, M = self.d, self.n_terms
+        H = np.zeros((d, d))
+        mu = np.zeros((d, d))
+        mup = np.zeros((d, d))
+        mum = np.zeros((d, d))
+        v = np.zeros(sum(x * x for x in self.dims))
+        nu = np.zeros(M)
+        c = np.zeros(2 * M)
+        n = np.zeros((self.n_ado, M), dtype=np.int32)
+        tm = np.zeros(M, dtype=np.int32)
+        _check(_lib.heom_model_operators(self.handle, _ptr(H), _ptr(mu), _ptr(mup), _ptr(mum),
+                                         _ptr(v), _ptr(nu), _ptr(c), _ptr(n), _ptr(tm)))
+        vs, off = [], 0
+        for ds in self.dims:
+            vs.append(v[off:off + ds * ds].reshape(ds, ds))
+            off += ds * ds
+        return {"H": H, "mu": mu, "mu_plus": mup, "mu_minus": mum, "v": vs, "nu": nu,
+                "c": c[0::2] + 1j * c[1::2], "ado_n": n, "term_mode": tm}
+
+
+class State:
+    """A device hierarchy of n_traj trajectories."""
+
+    def __init__(self, model: Model, n_traj=1, precision="fp64", handle=None):
+        self.model = model
+        if handle is None:
+            h = C.c_void_p()
+            _check(_lib.heom_state_create(model.handle, int(n_traj), _PREC[precision], C.byref(h)))
+            handle = h
+        self.handle = handle
+        nt, pr = C.c_int(), C.c_int()
+        _check(_lib.heom_state_shape(self.handle, C.byref(nt), C.byref(pr)))
+        self.n_traj, self.precision = nt.value, pr.value
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.heom_state_free(self.handle)
+            self.handle = None
+
+    @property
+    def shape(self):
+        m = self.model
+        return (self.n_traj, m.n_ado, m.d, m.d)
+
+    def upload(self, x):
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).reshape(self.shape))
+        _check(_lib.heom_state_upload(self.handle, _ptr(x)))
+
+    def download(self):
+        out = np.zeros(self.shape, dtype=np.complex128)
+        _check(_lib.heom_state_download(self.handle, _ptr(out)))
+        return out
+
+    def upload_range(self, first, x):
+        m = self.model
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).reshape(-1, m.n_ado, m.d, m.d))
+        _check(_lib.heom_state_upload_range(self.handle, int(first), x.shape[0], _ptr(x)))
+
+    def download_range(self, first, count):
+        m = self.model
+        out = np.zeros((count, m.n_ado, m.d, m.d), dtype=np.complex128)
+        _check(_lib.heom_state_download_range(self.handle, int(first), int(count), _ptr(out)))
+        return out
+
+    def set_ground(self):
+        _check(_lib.heom_state_set_ground(self.handle))
+
+    def copy_from(self, other: "State"):
+        _check(_lib.heom_state_copy(self.handle, other.handle))
+
+
+# ----------------------------------------------------- C-named functions --
+
+def heom_model_build(params, stream=None) -> Model:
+    return Model(params, stream=stream, device=True)
+
+
+def heom_model_build_host(params) -> Model:
+    return Model(params, device=False)
+
+
+def heom_state_create(model, n_traj=1, precision="fp64") -> State:
+    return State(model, n_traj, precision)
+
+
+def heom_rhs(model, x_in: State, x_out: State, adjoint=False):
+    _check(_lib.heom_rhs(model.handle, x_in.handle, x_out.handle, int(bool(adjoint))))
+
+
+def heom_propagate(model, state: State, n_steps: int, adjoint=False):
+    _check(_lib.heom_propagate(model.handle, state.handle, int(n_steps), int(bool(adjoint))))
+
+
+def heom_apply_dipole(model, state: State, op="mu", transpose=False):
+    _check(_lib.heom_apply_dipole(model.handle, state.handle, _OPS.get(op, op), int(bool(transpose))))
+
+
+def heom_trace(model, state: State, op="mu"):
+    out = np.zeros(2 * state.n_traj)
+    _check(_lib.heom_trace(model.handle, state.handle, _OPS.get(op, op), _ptr(out)))
+    return out[0::2] + 1j * out[1::2]
+
+
+def heom_residual(model, state: State):
+    r = C.c_double()
+    _check(_lib.heom_residual(model.handle, state.handle, C.byref(r)))
+    return r.value
+
+
+def heom_equilibrate(model, tol=1e-10, check_every=100, min_steps=0, max_steps=10000,
+                     require_convergence=False):
+    h = C.c_void_p()
+    steps, res = C.c_int(), C.c_double()
+    rc = _lib.heom_equilibrate(model.handle, float(tol), int(check_every), int(min_steps),
+                               int(max_steps), int(bool(require_convergence)), C.byref(h),
+                               C.byref(steps), C.byref(res))
+    if rc == HEOM_ERR_NOCONV and h.value:
+        _lib.heom_state_free(h)
+    _check(rc)
+    return State(model, handle=h), steps.value, res.value
+
+
+def heom_linear_response(model, rho_eq: State, n: int, steps_per_sample: int, precision="fp64"):
+    out = np.zeros(2 * n)
+    _check(_lib.heom_linear_response(model.handle, rho_eq.handle, int(n), int(steps_per_sample),
+                                     _PREC[precision], _ptr(out)))
+    return out[0::2] + 1j * out[1::2]
+
+
+def heom_response_2d(model, rho_eq: State, grid, precision="fp64", method="direct", max_batch=0):
+    """R[t2][pathway (I, II)][t1][t3] as complex128."""
+    t2 = (C.c_int * len(grid["t2_steps"]))(*[int(s) for s in grid["t2_steps"]])
+    g = heom_grid(int(grid["n1"]), int(grid["n3"]), int(grid["steps_per_sample"]),
+                  len(grid["t2_steps"]), t2)
+    n_t2 = len(grid["t2_steps"])
+    out = np.zeros(n_t2 * 2 * grid["n1"] * grid["n3"] * 2)
+    _check(_lib.heom_response_2d(model.handle, rho_eq.handle, C.byref(g), _PREC[precision],
+                                 _METHOD[method], int(max_batch), _ptr(out)))
+    z = out[0::2] + 1j * out[1::2]
+    return z.reshape(n_t2, 2, grid["n1"], grid["n3"])
+
+
+def heom_spectrum_2d(R_I, R_II, dt_s):
+    R_I = np.ascontiguousarray(np.asarray(R_I, dtype=np.complex128))
+    R_II = np.ascontiguousarray(np.asarray(R_II, dtype=np.complex128))
+    n1, n3 = R_I.shape
+    S = np.zeros((2 * n3, 2 * n1))
+    _check(load_library().heom_spectrum_2d(_ptr(R_I), _ptr(R_II), n1, n3, float(dt_s), _ptr(S)))
+    return S
+
+
+def heom_timing_enable(model, enable=True):
+    _check(_lib.heom_timing_enable(model.handle, int(bool(enable))))
+
+
+def heom_timing_read(model):
+    ms, n, upd = C.c_double(), C.c_longlong(), C.c_longlong()
+    _check(_lib.heom_timing_read(model.handle, C.byref(ms), C.byref(n), C.byref(upd)))
+    return ms.value, n.value, upd.value
