@@ -80,8 +80,8 @@ __global__ __launch_bounds__(NT) void rhs_generic_kernel(DevOps<T> op, const T* 
       const int a = e / d, c = e - (e / d) * d;
       T s = T(0);
       for (int k = 0; k < d; ++k) s += H[a * d + k] * sm[k * d + c] - sm[a * d + k] * H[k * d + c];
-      accI[i] = -s - g * sm[e];
-      accR[i] -= g * rin[dd + e];
+      accI[i] = -s - g * rin[dd + e];
+      accR[i] -= g * sm[e];
     }
   }
   // couplings to the hierarchy neighbours through V_s
