@@ -88,6 +88,7 @@ def main():
     ap.add_argument("--spectrum", type=int, default=1, help="also time one full 2D spectrum")
     ap.add_argument("--eq-steps", type=int, default=200)
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "mfma", "mfma_dyn"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path shards into independent "
@@ -103,6 +104,13 @@ def main():
     stream = torch.cuda.current_stream()
     m = P.heom_model_build(params, stream=stream.cuda_stream)
     B = args.batch
+    tune = None
+    if args.kernel == "auto":
+        best, ms = P.heom_autotune(m, min(B, 8), args.precision, reps=1)
+        tune = {"chosen": best, "ms_per_step_8traj": ms}
+    else:
+        P.heom_model_set_kernel(m, args.precision, args.kernel)
+    kernel = P.heom_model_get_kernel(m, args.precision)
     s = P.State(m, B, args.precision)
     s.set_ground()
     P.heom_propagate(m, s, args.warmup)
@@ -140,10 +148,13 @@ def main():
         "config": {"workload": f"3-mode MAB HEOM, 80 states, K=2 Pade x3, depth {args.depth} "
                                f"({m.n_ado} ADOs), {B} trajectories batched, RK4 dt=0.1",
                    "n_ado": m.n_ado, "d": m.d, "trajectories": B},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": "rhs_generic_kernel (fused RHS + RK4 stage)",
+        "roofline": {"bound": "alu" if kernel == "generic" else "mfma", "achieved": achieved,
+                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "kernel": ("rhs_generic_kernel" if kernel == "generic" else "rhs_mfma_kernel")
+                               + " (fused RHS + RK4 stage)",
                      "avg_launch_ms": avg_launch_s * 1e3, "launches": n_launch},
+        "kernel_choice": kernel,
+        "autotune": tune,
     }
 
     if args.spectrum:

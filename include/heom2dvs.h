@@ -224,6 +224,34 @@ int heom_response_2d(heom_model* model, const heom_state* rho_eq, const heom_gri
 int heom_spectrum_2d(const double* R_I, const double* R_II, int n1, int n3, double dt_s,
                      double* S_out);
 
+/* ------------------------------------------------------ kernel choice -- */
+/* Implementations of the fused RHS / RK4-stage kernel:
+ *   HEOM_KERNEL_GENERIC : VALU kernel, one workgroup of 64/256 threads per
+ *                         matrix, any d <= 128.
+ *   HEOM_KERNEL_MFMA    : matrix-core kernel (v_mfma 16x16x4, persistent
+ *                         workgroups of ceil(d/16) waves), d zero-padded to a
+ *                         multiple of 16; compile-time mode shapes for
+ *                         (4,4,5), (5,5) and (6) levels, runtime shape otherwise.
+ *   HEOM_KERNEL_MFMA_DYN: the matrix-core kernel with the runtime mode shape
+ *                         even where a compile-time one exists.
+ * Models start on HEOM_KERNEL_MFMA where it fits the LDS (FP32 d <= 112,
+ * FP64 d <= 80) and on HEOM_KERNEL_GENERIC otherwise; heom_autotune measures
+ * the candidates. */
+typedef enum {
+  HEOM_KERNEL_AUTO = 0,
+  HEOM_KERNEL_GENERIC = 1,
+  HEOM_KERNEL_MFMA = 2,
+  HEOM_KERNEL_MFMA_DYN = 3
+} heom_kernel;
+int heom_model_set_kernel(heom_model* model, int precision, int kernel);
+int heom_model_get_kernel(const heom_model* model, int precision, int* kernel_out);
+/* Times every kernel variant on a scratch batch of n_traj trajectories in
+ * the given precision (reps RK4 steps each) and keeps the fastest for this
+ * model and precision.  ms_out (may be NULL) receives the measured time per
+ * RK4 step of each variant, indexed by heom_kernel (entry 0 unused). */
+int heom_autotune(heom_model* model, int n_traj, int precision, int reps, int* kernel_out,
+                  double* ms_out);
+
 /* ------------------------------------------------------- measurement -- */
 /* While enabled, every launch of the fused RHS/RK4-stage kernel on this model
  * is bracketed by HIP events on the model's stream; heom_timing_read returns

@@ -1,6 +1,6 @@
 """Compile the gfx950 HIP library libheom2dvs.so in-tree (hipcc, no JIT).
 
-Usage: python -m paper_2601_20550_amd.build   (or __graft_entry__.build()).
+Usage: python -c "import __graft_entry__ as g; g.build()" (loads this file by path).
 Objects go to _build/ at the repository root; the shared library is written
 next to this file so the binding finds it.
 """

@@ -129,6 +129,8 @@ struct heom_model {
   int lds_limit = 65536;
   // device copies
   DevBuf H64, H32, v64, v32, g64, g32, mu64[3];
+  DevBuf Hp64, Hp32;  // H zero-padded to a multiple of 16 (matrix-core kernel)
+  int kernel[2] = {HEOM_KERNEL_MFMA, HEOM_KERNEL_MFMA};  // per precision
   DevBuf nb_ptr[2], nb_idx[2], nb_a64[2], nb_a32[2];
   heom::DevOps<double> ops64[2];
   heom::DevOps<float> ops32[2];
@@ -232,6 +234,16 @@ void upload_model(heom_model* m) {
     fill(m->ops64[dir], m->H64, m->v64, m->g64, m->nb_a64[dir]);
     fill(m->ops32[dir], m->H32, m->v32, m->g32, m->nb_a32[dir]);
   }
+  {
+    const int d = hm.d, DP = 16 * ((d + 15) / 16);
+    std::vector<double> hp(static_cast<size_t>(DP) * DP, 0.0);
+    for (int a = 0; a < d; ++a)
+      for (int c = 0; c < d; ++c) hp[static_cast<size_t>(a) * DP + c] = hm.H[static_cast<size_t>(a) * d + c];
+    m->Hp64 = upload_vec(hp, st);
+    m->Hp32 = f32(hp);
+    if (!heom::mfma_supported<double>(d)) m->kernel[HEOM_FP64] = HEOM_KERNEL_GENERIC;
+    if (!heom::mfma_supported<float>(d)) m->kernel[HEOM_FP32] = HEOM_KERNEL_GENERIC;
+  }
   m->red_result = DevBuf(sizeof(double) * 4);
   m->has_device = true;
 }
@@ -255,19 +267,40 @@ std::pair<hipEvent_t, hipEvent_t> next_event_pair(heom_model* m) {
   return m->events[m->events_used++];
 }
 
+template <typename T>
+const T* padded_H(const heom_model* m);
+template <>
+const double* padded_H<double>(const heom_model* m) { return m->Hp64.as<double>(); }
+template <>
+const float* padded_H<float>(const heom_model* m) { return m->Hp32.as<float>(); }
+
+template <typename T>
+constexpr int prec_of() { return std::is_same<T, double>::value ? HEOM_FP64 : HEOM_FP32; }
+
+// One launch of the chosen RHS / RK4-stage kernel.
+template <typename T>
+void launch_stage(heom_model* m, bool adjoint, const T* in, const T* y, T* out, double coef, int n_traj) {
+  const auto& op = ops_of<T>(m, adjoint);
+  const int k = m->kernel[prec_of<T>()];
+  if (k == HEOM_KERNEL_GENERIC)
+    heom::launch_rhs<T>(op, in, y, out, coef, n_traj, m->stream);
+  else
+    heom::launch_rhs_mfma<T>(op, padded_H<T>(m), in, y, out, coef, n_traj, k == HEOM_KERNEL_MFMA_DYN ? 1 : 0,
+                             m->stream);
+}
+
 // One launch of the fused RHS / RK4-stage kernel (timed when enabled).
 template <typename T>
 void stage(heom_model* m, bool adjoint, const T* in, const T* y, T* out, double coef, int n_traj) {
-  const auto& op = ops_of<T>(m, adjoint);
   if (m->timing) {
     auto ev = next_event_pair(m);
     hip_check(hipEventRecord(ev.first, m->stream), "event record");
-    heom::launch_rhs<T>(op, in, y, out, coef, n_traj, m->stream);
+    launch_stage<T>(m, adjoint, in, y, out, coef, n_traj);
     hip_check(hipEventRecord(ev.second, m->stream), "event record");
     m->launches += 1;
     m->ado_updates += static_cast<long long>(n_traj) * m->hm.n_ado;
   } else {
-    heom::launch_rhs<T>(op, in, y, out, coef, n_traj, m->stream);
+    launch_stage<T>(m, adjoint, in, y, out, coef, n_traj);
   }
 }
 
@@ -324,7 +357,7 @@ template <typename T>
 double residual_of(heom_model* m, const T* x, int n_traj) {
   const long long elems = static_cast<long long>(n_traj) * m->traj_elems();
   T* w = scratch<T>(m, 0, elems);
-  heom::launch_rhs<T>(ops_of<T>(m, false), x, nullptr, w, 1.0, n_traj, m->stream);
+  launch_stage<T>(m, false, x, nullptr, w, 1.0, n_traj);
   return absmax<T>(m, w, static_cast<long long>(n_traj) * m->hm.n_ado);
 }
 
@@ -748,11 +781,9 @@ int heom_rhs(heom_model* m, const heom_state* in, heom_state* out, int adjoint) 
     if (in->n_traj != out->n_traj || in->precision != out->precision)
       throw HeomError(HEOM_ERR_STATE, "in/out shapes differ");
     if (in->precision == HEOM_FP64)
-      heom::launch_rhs<double>(ops_of<double>(m, adjoint != 0), in->buf.as<double>(), nullptr,
-                               out->buf.as<double>(), 1.0, in->n_traj, m->stream);
+      launch_stage<double>(m, adjoint != 0, in->buf.as<double>(), nullptr, out->buf.as<double>(), 1.0, in->n_traj);
     else
-      heom::launch_rhs<float>(ops_of<float>(m, adjoint != 0), in->buf.as<float>(), nullptr, out->buf.as<float>(),
-                              1.0, in->n_traj, m->stream);
+      launch_stage<float>(m, adjoint != 0, in->buf.as<float>(), nullptr, out->buf.as<float>(), 1.0, in->n_traj);
     hip_check(hipStreamSynchronize(m->stream), "sync");
   });
 }
@@ -927,6 +958,75 @@ int heom_spectrum_2d(const double* R_I, const double* R_II, int n1, int n3, doub
     heom::launch_spectrum(dI.as<double>(), dII.as<double>(), n1, n3, dt_s, work.as<double>(), S.as<double>(),
                           nullptr);
     hip_check(hipMemcpy(S_out, S.p, S.bytes, hipMemcpyDeviceToHost), "download");
+  });
+}
+
+int heom_model_set_kernel(heom_model* m, int precision, int kernel) {
+  return guarded([&] {
+    require_device(m);
+    if (precision != HEOM_FP64 && precision != HEOM_FP32) throw HeomError(HEOM_ERR_PARAM, "bad precision");
+    if (kernel < HEOM_KERNEL_AUTO || kernel > HEOM_KERNEL_MFMA_DYN) throw HeomError(HEOM_ERR_PARAM, "bad kernel");
+    const bool ok = precision == HEOM_FP64 ? heom::mfma_supported<double>(m->hm.d) : heom::mfma_supported<float>(m->hm.d);
+    if (kernel == HEOM_KERNEL_AUTO) kernel = ok ? HEOM_KERNEL_MFMA : HEOM_KERNEL_GENERIC;
+    if (kernel != HEOM_KERNEL_GENERIC && !ok) throw HeomError(HEOM_ERR_PARAM, "matrix-core kernel unsupported for this d");
+    m->kernel[precision] = kernel;
+  });
+}
+
+int heom_model_get_kernel(const heom_model* m, int precision, int* kernel_out) {
+  return guarded([&] {
+    require_device(m);
+    if ((precision != HEOM_FP64 && precision != HEOM_FP32) || !kernel_out) throw HeomError(HEOM_ERR_PARAM, "bad argument");
+    *kernel_out = m->kernel[precision];
+  });
+}
+
+int heom_autotune(heom_model* m, int n_traj, int precision, int reps, int* kernel_out, double* ms_out) {
+  return guarded([&] {
+    require_device(m);
+    if (n_traj < 1 || reps < 1) throw HeomError(HEOM_ERR_PARAM, "bad autotune sizes");
+    if (precision != HEOM_FP64 && precision != HEOM_FP32) throw HeomError(HEOM_ERR_PARAM, "bad precision");
+    auto s = new_state(m, n_traj, precision);
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    const int saved = m->kernel[precision];
+    const bool saved_timing = m->timing;
+    m->timing = false;
+    int best = saved;
+    double best_ms = 1e300;
+    const bool ok = precision == HEOM_FP64 ? heom::mfma_supported<double>(m->hm.d) : heom::mfma_supported<float>(m->hm.d);
+    for (int k = HEOM_KERNEL_GENERIC; k <= HEOM_KERNEL_MFMA_DYN; ++k) {
+      if (k != HEOM_KERNEL_GENERIC && !ok) continue;
+      m->kernel[precision] = k;
+      auto run = [&](int steps) {
+        if (precision == HEOM_FP64) {
+          heom::launch_set_ground<double>(s->buf.as<double>(), m->traj_elems(), n_traj, s->n_elems(), m->stream);
+          rk4_steps_scratch<double>(m, s->buf.as<double>(), n_traj, steps, false);
+        } else {
+          heom::launch_set_ground<float>(s->buf.as<float>(), m->traj_elems(), n_traj, s->n_elems(), m->stream);
+          rk4_steps_scratch<float>(m, s->buf.as<float>(), n_traj, steps, false);
+        }
+      };
+      run(1);  // warm-up (first launch configures the kernel)
+      hip_check(hipEventRecord(e0, m->stream), "event");
+      run(reps);
+      hip_check(hipEventRecord(e1, m->stream), "event");
+      hip_check(hipEventSynchronize(e1), "event sync");
+      float ms = 0.0f;
+      hip_check(hipEventElapsedTime(&ms, e0, e1), "event elapsed");
+      const double per = ms / reps;
+      if (ms_out) ms_out[k] = per;
+      if (per < best_ms) {
+        best_ms = per;
+        best = k;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    m->kernel[precision] = best;
+    m->timing = saved_timing;
+    if (kernel_out) *kernel_out = best;
   });
 }
 

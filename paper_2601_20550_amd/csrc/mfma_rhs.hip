@@ -1,0 +1,522 @@
+// Fused HEOM right-hand side + RK4 stage on the matrix cores (gfx950 MFMA).
+//
+// A persistent workgroup of NB = ceil(d/16) waves loops over (trajectory,
+// ADO) matrices and computes  out = y + coef * L(in)  for each.  Wave w owns
+// row block w (16 rows) of the zero-padded DP x DP output (DP = 16 NB) and
+// computes every term of those rows:
+//
+//   L rho = -i (H rho - rho H) - gamma_n rho + sum_s [ -i V_s X_s + i Y_s V_s ],
+//   X_s = sum_q aL_q rho_{m_q},   Y_s = sum_q conj(aL_q) rho_{m_q}
+//       = X_s - 2i sum_q Im(aL_q) rho_{m_q},
+//
+// with H real symmetric, V_s = v_s acting on mode s only, and the neighbour
+// lists (m_q, aL_q) of the host tables (aR = conj(aL) for every entry).
+//
+//   * H rho and rho H run on v_mfma 16x16x4 (FP32 or FP64): the fragment
+//     H[row block w][k-slice] stays in registers; rho (two real planes) and
+//     H (for the right product) are read from LDS.
+//   * The neighbour sums are formed from coalesced row-block loads (each
+//     neighbour matrix is read once per workgroup), staged in the rho planes
+//     of LDS, and contracted with v_s on the VALU.  The mode structure
+//     (kept levels and strides of every mode) is a compile-time Shape for the
+//     common cases, so the digit arithmetic of the Kronecker contractions is
+//     constant-folded; DynShape handles any other shape.
+#include <hip/hip_runtime.h>
+
+#include <stdexcept>
+#include <string>
+
+#include "kernels.h"
+
+namespace heom {
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Operand layouts (lane = 16 lq + lr): A[i][k] at lane i + 16 k, B[k][j] at
+// lane j + 16 k.  Accumulator element r of a lane holds row crow(lq, r) and
+// column lr: rows 4 lq .. 4 lq + 3 for the FP32 instruction, rows lq, lq + 4,
+// lq + 8, lq + 12 for the FP64 one.
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<float> {
+  using acc = f32x4;
+  __device__ static inline acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static constexpr int crow(int lq, int r) { return 4 * lq + r; }
+};
+
+template <>
+struct Mfma<double> {
+  using acc = f64x4;
+  __device__ static inline acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static constexpr int crow(int lq, int r) { return lq + 4 * r; }
+};
+
+// Mode structure known at compile time.
+template <int NM, int D0, int D1 = 1, int D2 = 1, int D3 = 1>
+struct StaticShape {
+  __device__ StaticShape(const int*, const int*, int, int) {}
+  __device__ static constexpr int nm() { return NM; }
+  __device__ static constexpr int dim(int s) { return s == 0 ? D0 : s == 1 ? D1 : s == 2 ? D2 : D3; }
+  __device__ static constexpr int stride(int s) {
+    return s == 0 ? D1 * D2 * D3 : s == 1 ? D2 * D3 : s == 2 ? D3 : 1;
+  }
+  __device__ static constexpr int d() { return D0 * D1 * D2 * D3; }
+  static bool matches(int nm_, const int* dims) {
+    if (nm_ != NM) return false;
+    const int D[4] = {D0, D1, D2, D3};
+    for (int s = 0; s < NM; ++s)
+      if (dims[s] != D[s]) return false;
+    return true;
+  }
+};
+
+// Mode structure read from the kernel arguments.
+struct DynShape {
+  int nm_, d_, dims_[4], strides_[4];
+  __device__ DynShape(const int* dims, const int* strides, int nm, int d) : nm_(nm), d_(d) {
+    for (int s = 0; s < 4; ++s) {
+      dims_[s] = dims[s];
+      strides_[s] = strides[s];
+    }
+  }
+  __device__ int nm() const { return nm_; }
+  __device__ int dim(int s) const { return dims_[s]; }
+  __device__ int stride(int s) const { return strides_[s]; }
+  __device__ int d() const { return d_; }
+};
+
+// LDS layout (elements of T): rho planes Re, Im and H, each DP x LD with
+// LD = DP + 1 so that column reads of the A operand hit distinct banks, then
+// v_s (4 x 64 values).
+template <typename T, int NB>
+struct Lds {
+  static constexpr int DP = 16 * NB;
+  static constexpr int LD = DP + 1;
+  static constexpr int PLANE = DP * LD;
+  static constexpr int HOFF = 2 * PLANE;
+  static constexpr int VOFF = HOFF + PLANE;
+  static constexpr size_t bytes = (VOFF + 4 * 64) * sizeof(T);
+};
+
+// Vector of VW elements of T (one 16-byte global access per lane when
+// VW * sizeof(T) = 16).
+template <typename T, int VW>
+struct Vec {
+  typedef T type __attribute__((ext_vector_type(VW)));
+};
+template <typename T>
+struct Vec<T, 1> {
+  typedef T type;
+};
+
+template <typename T, int VW>
+__device__ inline T vget(const typename Vec<T, VW>::type& v, int i) {
+  if constexpr (VW == 1) {
+    return v;
+  } else {
+    return v[i];
+  }
+}
+
+template <typename T, int VW>
+__device__ inline void vset(typename Vec<T, VW>::type& v, int i, T x) {
+  if constexpr (VW == 1) {
+    v = x;
+  } else {
+    v[i] = x;
+  }
+}
+
+template <typename T, int NB, typename Shape, int MINW, int VW>
+__global__ __launch_bounds__(NB * 64, MINW) void rhs_mfma_kernel(DevOps<T> op, const T* __restrict__ Hp,
+                                                                 const T* __restrict__ in, const T* y, T* out,
+                                                                 T coef, long long n_items) {
+  using L = Lds<T, NB>;
+  using M = Mfma<T>;
+  using acc_t = typename M::acc;
+  using vec_t = typename Vec<T, VW>::type;
+  constexpr int DP = L::DP, LD = L::LD;
+  constexpr int NT = NB * 64;
+  // vectors per lane covering a 16-row block of DP columns
+  constexpr int RV = (16 * DP + VW * 64 - 1) / (VW * 64);
+  extern __shared__ unsigned char smem_raw[];
+  T* sRe = reinterpret_cast<T*>(smem_raw);
+  T* sIm = sRe + L::PLANE;
+  T* sH = sRe + L::HOFF;
+  T* sV = sRe + L::VOFF;
+
+  const Shape sh(op.dims, op.strides, op.n_modes, op.d);
+  const int d = sh.d();
+  const long long dd = static_cast<long long>(d) * d;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int rows0 = 16 * wave;
+  // elements of this wave's row block (rows rows0 .. rows0+15, clipped to d)
+  const int rb_rows = rows0 < d ? (d - rows0 < 16 ? d - rows0 : 16) : 0;
+  const int rb_elems = rb_rows * d;
+
+  // once per workgroup: H (padded) and v_s into LDS
+  for (int e = threadIdx.x; e < DP * DP; e += NT) {
+    const int r = e / DP, c = e - (e / DP) * DP;
+    sH[r * LD + c] = Hp[e];
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    if (s >= sh.nm()) break;
+    const int ds2 = sh.dim(s) * sh.dim(s);
+    for (int e = threadIdx.x; e < ds2; e += NT) sV[s * 64 + e] = op.v[op.v_off[s] + e];
+  }
+  // zero the padding rows/columns of the rho planes once; only the d x d
+  // block is rewritten per item
+  for (int e = threadIdx.x; e < 2 * L::PLANE; e += NT) sRe[e] = T(0);
+
+  for (long long item = blockIdx.x; item < n_items; item += gridDim.x) {
+    // Per-lane index arithmetic is redone for every item: an opaque copy of
+    // the lane id keeps the compiler from hoisting hundreds of LDS addresses
+    // of the unrolled loops out of the item loop (register pressure).
+    int lane_v = lane;
+    asm volatile("" : "+v"(lane_v));
+    const int lr = lane_v & 15;
+    const int lq = lane_v >> 4;
+    const int n = static_cast<int>(item % op.n_ado);
+    const long long base = item * 2 * dd;
+    const long long traj_base = (item - n) * 2 * dd;
+    const T* rin = in + base;
+
+    __syncthreads();  // previous item's LDS reads are complete
+    // ---- stage rho_n: 16-byte loads, d x d block of the LDS planes -------
+    for (int v = threadIdx.x; v * VW < dd; v += NT) {
+      const vec_t xr = *reinterpret_cast<const vec_t*>(rin + static_cast<long long>(v) * VW);
+      const vec_t xi = *reinterpret_cast<const vec_t*>(rin + dd + static_cast<long long>(v) * VW);
+      const int e = v * VW, r = e / d, c = e - (e / d) * d;
+#pragma unroll
+      for (int i = 0; i < VW; ++i) {
+        sRe[r * LD + c + i] = vget<T, VW>(xr, i);
+        sIm[r * LD + c + i] = vget<T, VW>(xi, i);
+      }
+    }
+    __syncthreads();
+
+    // ---- H commutator of row block w --------------------------------------
+    //   Re L += H Im - Im H,   Im L += Re H - H Re
+    acc_t Rre[NB], Rim[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      Rre[j] = acc_t{0, 0, 0, 0};
+      Rim[j] = acc_t{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4 * NB; ++kk) {
+      const int k = 4 * kk + lq;
+      const T hA = sH[(rows0 + lr) * LD + k];
+      const T nhA = -hA;
+      const T aRe = sRe[(rows0 + lr) * LD + k];
+      const T naIm = -sIm[(rows0 + lr) * LD + k];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const T hB = sH[k * LD + 16 * j + lr];
+        Rre[j] = M::mma(hA, sIm[k * LD + 16 * j + lr], Rre[j]);
+        Rre[j] = M::mma(naIm, hB, Rre[j]);
+        Rim[j] = M::mma(nhA, sRe[k * LD + 16 * j + lr], Rim[j]);
+        Rim[j] = M::mma(aRe, hB, Rim[j]);
+      }
+      // keep the scheduler from hoisting the LDS operands of many k-slices
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // damping
+    const T g = op.gamma[n];
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = rows0 + M::crow(lq, r), c = 16 * j + lr;
+        Rre[j][r] -= g * sRe[a * LD + c];
+        Rim[j][r] -= g * sIm[a * LD + c];
+      }
+
+    // ---- couplings to the hierarchy neighbours ----------------------------
+    // X_s is accumulated row block by row block directly in the LDS planes
+    // (each wave updates only its own rows) from 16-byte loads.
+#pragma unroll 1
+    for (int s = 0; s < 4; ++s) {
+      if (s >= sh.nm()) break;
+      const int p0 = op.nb_ptr[n * op.n_modes + s];
+      const int p1 = op.nb_ptr[n * op.n_modes + s + 1];
+      if (p0 == p1) continue;  // uniform across the workgroup
+      const int ds = sh.dim(s), st = sh.stride(s);
+      const T* vs = sV + s * 64;
+      // X_s (and W = sum_q Im(aL_q) rho_q, for Y_s) of this wave's rows in
+      // registers, one 16-byte load per vector and neighbour
+      vec_t xr[RV], xi[RV], wr[RV], wi[RV];
+      bool have_w = false;
+#pragma unroll
+      for (int k = 0; k < RV; ++k) {
+#pragma unroll
+        for (int i = 0; i < VW; ++i) {
+          vset<T, VW>(xr[k], i, T(0));
+          vset<T, VW>(xi[k], i, T(0));
+          vset<T, VW>(wr[k], i, T(0));
+          vset<T, VW>(wi[k], i, T(0));
+        }
+      }
+      for (int q = p0; q < p1; ++q) {
+        const T* rm = in + traj_base + static_cast<long long>(op.nb_idx[q]) * 2 * dd + rows0 * d;
+        const T ar = op.nb_a[4 * q], ai = op.nb_a[4 * q + 1];
+        const bool cplx = ai != T(0);
+        have_w = have_w || cplx;
+#pragma unroll
+        for (int k = 0; k < RV; ++k) {
+          const int e = (lane + 64 * k) * VW;
+          if (e < rb_elems) {
+            const vec_t br = *reinterpret_cast<const vec_t*>(rm + e);
+            const vec_t bi = *reinterpret_cast<const vec_t*>(rm + dd + e);
+            xr[k] += ar * br - ai * bi;
+            xi[k] += ar * bi + ai * br;
+            if (cplx) {
+              wr[k] += ai * br;
+              wi[k] += ai * bi;
+            }
+          }
+        }
+      }
+      __syncthreads();  // every wave is done with the previous LDS content
+#pragma unroll
+      for (int k = 0; k < RV; ++k) {
+        const int e = (lane + 64 * k) * VW;
+        if (e < rb_elems) {
+          const int r = rows0 + e / d, c = e - (e / d) * d;
+#pragma unroll
+          for (int i = 0; i < VW; ++i) {
+            sRe[r * LD + c + i] = vget<T, VW>(xr[k], i);
+            sIm[r * LD + c + i] = vget<T, VW>(xi[k], i);
+          }
+        }
+      }
+      __syncthreads();
+      // left product: (V_s X_s)[a][c] = sum_k v_s[a_s][k] X_s[a + (k - a_s) st][c];  L += -i V X
+      {
+        int as[4], r0[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = rows0 + M::crow(lq, r);
+          as[r] = (a / st) % ds;
+          r0[r] = a - as[r] * st;
+        }
+        for (int k = 0; k < ds; ++k) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const T v = vs[as[r] * ds + k];
+            const int rowoff = (r0[r] + k * st) * LD + lr;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+              Rre[j][r] += v * sIm[rowoff + 16 * j];
+              Rim[j][r] -= v * sRe[rowoff + 16 * j];
+            }
+          }
+        }
+      }
+      __syncthreads();  // left products read other waves' rows
+      // Y_s = X_s - 2i W on this wave's rows
+      if (have_w) {
+#pragma unroll
+        for (int k = 0; k < RV; ++k) {
+          const int e = (lane + 64 * k) * VW;
+          if (e < rb_elems) {
+            const int r = rows0 + e / d, c = e - (e / d) * d;
+#pragma unroll
+            for (int i = 0; i < VW; ++i) {
+              sRe[r * LD + c + i] = vget<T, VW>(xr[k], i) + 2 * vget<T, VW>(wi[k], i);
+              sIm[r * LD + c + i] = vget<T, VW>(xi[k], i) - 2 * vget<T, VW>(wr[k], i);
+            }
+          }
+        }
+      }
+      __syncthreads();
+      // right product: (Y_s V_s)[a][c] = sum_k Y_s[a][c + (k - c_s) st] v_s[k][c_s];  L += i Y V
+      {
+        int cs[NB], c0[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const int c = 16 * j + lr;
+          cs[j] = (c / st) % ds;
+          c0[j] = c - cs[j] * st;
+        }
+        for (int k = 0; k < ds; ++k) {
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            const T v = vs[k * ds + cs[j]];
+            const int coloff = c0[j] + k * st;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int a = rows0 + M::crow(lq, r);
+              Rre[j][r] -= v * sIm[a * LD + coloff];
+              Rim[j][r] += v * sRe[a * LD + coloff];
+            }
+          }
+        }
+      }
+    }
+
+    // ---- epilogue: out = y + coef * L ---------------------------------------
+    // transpose this wave's rows through LDS so that y and out move in
+    // 16-byte vectors
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = rows0 + M::crow(lq, r), c = 16 * j + lr;
+        sRe[a * LD + c] = Rre[j][r];
+        sIm[a * LD + c] = Rim[j][r];
+      }
+    __syncthreads();
+    {
+      const long long ob = base + rows0 * d;
+      vec_t yr[RV], yi[RV];
+      if (y) {
+#pragma unroll
+        for (int k = 0; k < RV; ++k) {
+          const int e = (lane + 64 * k) * VW;
+          if (e < rb_elems) {
+            yr[k] = *reinterpret_cast<const vec_t*>(y + ob + e);
+            yi[k] = *reinterpret_cast<const vec_t*>(y + ob + dd + e);
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < RV; ++k) {
+        const int e = (lane + 64 * k) * VW;
+        if (e < rb_elems) {
+          const int r = rows0 + e / d, c = e - (e / d) * d;
+          vec_t orr, oi;
+#pragma unroll
+          for (int i = 0; i < VW; ++i) {
+            T lre = sRe[r * LD + c + i], lim = sIm[r * LD + c + i];
+            if (y) {
+              lre = vget<T, VW>(yr[k], i) + coef * lre;
+              lim = vget<T, VW>(yi[k], i) + coef * lim;
+            }
+            vset<T, VW>(orr, i, lre);
+            vset<T, VW>(oi, i, lim);
+          }
+          *reinterpret_cast<vec_t*>(out + ob + e) = orr;
+          *reinterpret_cast<vec_t*>(out + ob + dd + e) = oi;
+        }
+      }
+    }
+  }
+}
+
+int g_cu_count = 0;
+
+int cu_count() {
+  if (g_cu_count == 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      g_cu_count = prop.multiProcessorCount;
+    if (g_cu_count <= 0) g_cu_count = 256;
+  }
+  return g_cu_count;
+}
+
+template <typename T, int NB, typename Shape, int VW>
+void launch_shape_vw(const DevOps<T>& op, const T* Hp, const T* in, const T* y, T* out, T coef, long long n_items,
+                     int wg_per_cu, hipStream_t stream) {
+  const size_t lds = Lds<T, NB>::bytes;
+  constexpr int MINW = (sizeof(T) == 4) ? 2 : 1;
+  auto kern = &rhs_mfma_kernel<T, NB, Shape, MINW, VW>;
+  static bool configured = false;
+  if (!configured) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              static_cast<int>(lds));
+    configured = true;
+  }
+  long long grid = static_cast<long long>(cu_count()) * wg_per_cu;
+  if (grid > n_items) grid = n_items;
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(NB * 64), lds, stream, op, Hp, in, y, out, coef,
+                     n_items);
+}
+
+// 16-byte vectors when every row starts on a 16-byte boundary
+template <typename T, int NB, typename Shape>
+void launch_shape(const DevOps<T>& op, const T* Hp, const T* in, const T* y, T* out, T coef, long long n_items,
+                  int wg_per_cu, hipStream_t stream) {
+  constexpr int VW = 16 / sizeof(T);
+  if (op.d % VW == 0)
+    launch_shape_vw<T, NB, Shape, VW>(op, Hp, in, y, out, coef, n_items, wg_per_cu, stream);
+  else
+    launch_shape_vw<T, NB, Shape, 1>(op, Hp, in, y, out, coef, n_items, wg_per_cu, stream);
+}
+
+template <typename T, int NB>
+void launch_dyn(const DevOps<T>& op, const T* Hp, const T* in, const T* y, T* out, T coef, long long n_items,
+                int wg_per_cu, hipStream_t stream) {
+  launch_shape<T, NB, DynShape>(op, Hp, in, y, out, coef, n_items, wg_per_cu, stream);
+}
+
+}  // namespace
+
+template <typename T>
+bool mfma_supported(int d) {
+  if (d < 1 || d > 128) return false;
+  const int NB = (d + 15) / 16;
+  const size_t DP = 16 * NB;
+  const size_t lds = (3 * DP * (DP + 1) + 4 * 64) * sizeof(T);
+  return lds <= 160 * 1024;
+}
+
+template <typename T>
+void launch_rhs_mfma(const DevOps<T>& op, const T* Hp, const T* in, const T* y, T* out, double coef, int n_traj,
+                     int variant, hipStream_t stream) {
+  const long long n_items = static_cast<long long>(n_traj) * op.n_ado;
+  if (n_items == 0) return;
+  const T c = static_cast<T>(coef);
+  // persistent grid: as many workgroups per CU as fit in LDS (160 KB)
+  const size_t DP = 16 * ((op.d + 15) / 16);
+  const size_t lds = (3 * DP * (DP + 1) + 4 * 64) * sizeof(T);
+  int wg = static_cast<int>((160 * 1024) / lds);
+  if (wg < 1) wg = 1;
+  if (wg > 8) wg = 8;
+  const bool specialised = variant != 1;
+  // compile-time shapes of the common workloads
+  if (specialised && StaticShape<3, 4, 4, 5>::matches(op.n_modes, op.dims)) {
+    launch_shape<T, 5, StaticShape<3, 4, 4, 5>>(op, Hp, in, y, out, c, n_items, wg, stream);
+  } else if (specialised && StaticShape<2, 5, 5>::matches(op.n_modes, op.dims)) {
+    launch_shape<T, 2, StaticShape<2, 5, 5>>(op, Hp, in, y, out, c, n_items, wg, stream);
+  } else if (specialised && StaticShape<1, 6>::matches(op.n_modes, op.dims)) {
+    launch_shape<T, 1, StaticShape<1, 6>>(op, Hp, in, y, out, c, n_items, wg, stream);
+  } else {
+    switch ((op.d + 15) / 16) {
+      case 1: launch_dyn<T, 1>(op, Hp, in, y, out, c, n_items, wg, stream); break;
+      case 2: launch_dyn<T, 2>(op, Hp, in, y, out, c, n_items, wg, stream); break;
+      case 3: launch_dyn<T, 3>(op, Hp, in, y, out, c, n_items, wg, stream); break;
+      case 4: launch_dyn<T, 4>(op, Hp, in, y, out, c, n_items, wg, stream); break;
+      case 5: launch_dyn<T, 5>(op, Hp, in, y, out, c, n_items, wg, stream); break;
+      case 6: launch_dyn<T, 6>(op, Hp, in, y, out, c, n_items, wg, stream); break;
+      case 7: launch_dyn<T, 7>(op, Hp, in, y, out, c, n_items, wg, stream); break;
+      case 8: launch_dyn<T, 8>(op, Hp, in, y, out, c, n_items, wg, stream); break;
+      default: throw std::runtime_error("MFMA RHS kernel supports d <= 128");
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw std::runtime_error(std::string("mfma rhs kernel: ") + hipGetErrorString(e));
+}
+
+template bool mfma_supported<float>(int);
+template bool mfma_supported<double>(int);
+template void launch_rhs_mfma<float>(const DevOps<float>&, const float*, const float*, const float*, float*,
+                                     double, int, int, hipStream_t);
+template void launch_rhs_mfma<double>(const DevOps<double>&, const double*, const double*, const double*,
+                                      double*, double, int, int, hipStream_t);
+
+}  // namespace heom

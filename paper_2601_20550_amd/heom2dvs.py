@@ -30,6 +30,9 @@ HEOM_FP64, HEOM_FP32 = 0, 1
 HEOM_PADE, HEOM_MATSUBARA = 0, 1
 HEOM_OP_MU, HEOM_OP_MU_PLUS, HEOM_OP_MU_MINUS = 0, 1, 2
 HEOM_RESP_DIRECT, HEOM_RESP_ADJOINT = 0, 1
+HEOM_KERNEL_AUTO, HEOM_KERNEL_GENERIC, HEOM_KERNEL_MFMA, HEOM_KERNEL_MFMA_DYN = 0, 1, 2, 3
+KERNELS = {"auto": 0, "generic": 1, "mfma": 2, "mfma_dyn": 3}
+KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
 
 _PREC = {"fp64": HEOM_FP64, "fp32": HEOM_FP32, HEOM_FP64: HEOM_FP64, HEOM_FP32: HEOM_FP32}
 _OPS = {"mu": HEOM_OP_MU, "mu_plus": HEOM_OP_MU_PLUS, "mu_minus": HEOM_OP_MU_MINUS}
@@ -107,6 +110,10 @@ _SIGS = {
                                    C.c_int, C.c_int, C.c_void_p]),
     "heom_spectrum_2d": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_double,
                                    C.c_void_p]),
+    "heom_model_set_kernel": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    "heom_model_get_kernel": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
+    "heom_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int),
+                                C.c_void_p]),
     "heom_timing_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "heom_timing_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
                                    C.POINTER(C.c_longlong)]),
@@ -122,7 +129,7 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with "
-                          "`python -m paper_2601_20550_amd.build` (there is no CPU fallback)")
+                          "__graft_entry__.build() (there is no CPU fallback)")
     lib = C.CDLL(path)
     for name, (res, args) in _SIGS.items():
         f = getattr(lib, name)
@@ -387,6 +394,26 @@ def heom_spectrum_2d(R_I, R_II, dt_s):
     S = np.zeros((2 * n3, 2 * n1))
     _check(load_library().heom_spectrum_2d(_ptr(R_I), _ptr(R_II), n1, n3, float(dt_s), _ptr(S)))
     return S
+
+
+def heom_model_set_kernel(model, precision, kernel):
+    _check(_lib.heom_model_set_kernel(model.handle, _PREC[precision], KERNELS.get(kernel, kernel)))
+
+
+def heom_model_get_kernel(model, precision):
+    k = C.c_int()
+    _check(_lib.heom_model_get_kernel(model.handle, _PREC[precision], C.byref(k)))
+    return KERNEL_NAMES[k.value]
+
+
+def heom_autotune(model, n_traj, precision="fp32", reps=2):
+    """Times the kernel variants; returns (chosen name, {name: ms per RK4 step})."""
+    k = C.c_int()
+    ms = np.full(4, np.nan)
+    _check(_lib.heom_autotune(model.handle, int(n_traj), _PREC[precision], int(reps), C.byref(k),
+                              _ptr(ms)))
+    return KERNEL_NAMES[k.value], {KERNEL_NAMES[i]: float(ms[i]) for i in (1, 2, 3)
+                                    if np.isfinite(ms[i])}
 
 
 def heom_timing_enable(model, enable=True):

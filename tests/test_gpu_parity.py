@@ -52,13 +52,18 @@ def _relerr(a, b):
 CASES = [("cfg1", None), ("cfg2", None), ("cfg2", 2), ("cfg3", 2)]
 
 
+KERNELS = ["generic", "mfma", "mfma_dyn"]
+
+
 @pytest.mark.parametrize("which,depth", CASES)
 @pytest.mark.parametrize("adjoint", [False, True])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_rhs_parity(which, depth, adjoint, prec):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_rhs_parity(which, depth, adjoint, prec, kernel):
     params = _params(which, depth)
     o = om.build(params)
     m = P.heom_model_build(params)
+    P.heom_model_set_kernel(m, prec, kernel)
     x = w.random_hierarchy(3, len(o.hier), o.d, seed=11, scale_by_depth=_depth_scale(o))
     xin = P.State(m, 3, prec)
     xout = P.State(m, 3, prec)
@@ -74,20 +79,24 @@ def test_rhs_parity_full_depth_three_modes():
     params = _params("cfg3")
     o = om.build(params)
     m = P.heom_model_build(params)
-    x = w.random_hierarchy(1, len(o.hier), o.d, seed=5, scale_by_depth=_depth_scale(o))
+    x = w.random_hierarchy(2, len(o.hier), o.d, seed=5, scale_by_depth=_depth_scale(o))
     ref = oh.rhs(o, x)
-    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-6)):
-        a, b = P.State(m, 1, prec), P.State(m, 1, prec)
-        a.upload(x)
-        P.heom_rhs(m, a, b)
-        assert _relerr(b.download(), ref) < tol, prec
+    for kernel in KERNELS:
+        for prec, tol in (("fp64", 1e-12), ("fp32", 2e-6)):
+            P.heom_model_set_kernel(m, prec, kernel)
+            a, b = P.State(m, 2, prec), P.State(m, 2, prec)
+            a.upload(x)
+            P.heom_rhs(m, a, b)
+            assert _relerr(b.download(), ref) < tol, (kernel, prec)
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
-def test_rk4_steps_parity(prec, tol):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_rk4_steps_parity(prec, tol, kernel):
     params = _params("cfg2", 3)
     o = om.build(params)
     m = P.heom_model_build(params)
+    P.heom_model_set_kernel(m, prec, kernel)
     x = w.random_hierarchy(2, len(o.hier), o.d, seed=3, hermitian=True, scale_by_depth=_depth_scale(o))
     s = P.State(m, 2, prec)
     s.upload(x)
@@ -220,6 +229,25 @@ def test_response_2d_parity(which, depth, n, sps, t2, dt, method):
     assert _relerr(got, ref) < 1e-10
     got32 = P.heom_response_2d(m, rho, grid, "fp32", method)
     assert _relerr(got32, ref) < 1e-4
+
+
+def test_response_2d_generic_kernel():
+    m, rho, grid, ref = _response_case("cfg2", 2, 6, 5, [0, 12], None)
+    for prec in ("fp64", "fp32"):
+        P.heom_model_set_kernel(m, prec, "generic")
+    got = P.heom_response_2d(m, rho, grid, "fp64", "adjoint")
+    assert _relerr(got, ref) < 1e-10
+    got32 = P.heom_response_2d(m, rho, grid, "fp32", "direct")
+    assert _relerr(got32, ref) < 1e-4
+
+
+def test_autotune_picks_a_measured_kernel():
+    params = _params("cfg2", 3)
+    m = P.heom_model_build(params)
+    best, ms = P.heom_autotune(m, 4, "fp32", reps=1)
+    assert set(ms) == {"generic", "mfma", "mfma_dyn"}
+    assert best == min(ms, key=ms.get)
+    assert P.heom_model_get_kernel(m, "fp32") == best
 
 
 def test_response_2d_batching_and_methods_agree():
