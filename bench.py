@@ -26,6 +26,14 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# HBM traffic of the matrix-core kernel per launch at the default workload, from
+# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs (profiles/rhs_mfma_kernel_3mode_L6_b128_fp32.md),
+# scaled by the counters' readings for kernels of known size.  Keyed by the
+# kernel source hash: a changed kernel reports traffic null until re-profiled.
+PROFILED_TRAFFIC = {
+    "87c1b457b77a58d3": {"read_GB": 289.2, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
+}
+
 PEAKS = {  # MI355X published dense peaks
     "fp32_tflops": 157.3,
     "fp64_tflops": 78.6,
@@ -49,6 +57,12 @@ def algorithmic_flops_per_rhs(model):
     n_down = int((n > 0).sum())
     per_ado = 8 * d ** 3 + 8 * d * d * sum(model.dims) + 6 * d * d
     return per_ado * model.n_ado + d * d * (2 * n_up + 16 * n_down)
+
+
+def kernel_source_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2601_20550_amd", "csrc", "mfma_rhs.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
 def cpu_baseline(params, budget_s=30.0):
@@ -154,8 +168,16 @@ def main():
                                + " (fused RHS + RK4 stage)",
                      "avg_launch_ms": avg_launch_s * 1e3, "launches": n_launch},
         "kernel_choice": kernel,
+        "kernel_source": kernel_source_hash(),
         "autotune": tune,
     }
+
+    prof = PROFILED_TRAFFIC.get(kernel_source_hash())
+    if (prof and kernel.startswith("mfma") and prof["batch"] == B
+            and prof["precision"] == args.precision and args.depth == 6):
+        line["roofline"]["traffic"] = (prof["read_GB"] + prof["write_GB"]) * 1e9
+        line["roofline"]["traffic_unit"] = "bytes per launch (HBM, calibrated rocprofv3 counters)"
+        line["roofline"]["hbm_GBs_at_traffic"] = line["roofline"]["traffic"] / avg_launch_s / 1e9
 
     if args.spectrum:
         rho, eq_steps, eq_res = P.heom_equilibrate(m, tol=0.0, check_every=args.eq_steps,
