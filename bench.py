@@ -91,6 +91,42 @@ def cpu_baseline(params, budget_s=30.0):
                       f"{len(o.hier)}-ADO model ({dt:.1f} s each); 4 RHS = 1 RK4 step"}
 
 
+def multi_instance(P, torch, precision, stream):
+    """The uneven 64-instance batch (d = 6, 25, 80; 35..5005 ADOs; 64x64 grid at
+    t2 = 0): seconds for all 64 responses batched (one launch per size class
+    and RK4 stage) and one instance after another, and their agreement."""
+    import workloads as w
+    insts = w.cfg4_instances()
+    models = [P.heom_model_build(p, stream=stream) for p, _ in insts]
+    grid = insts[0][1]
+    rhos = []
+    for m in models:
+        r = P.State(m, 1, "fp64")
+        r.set_ground()
+        rhos.append(r)
+    b = P.heom_batch_create(models)
+    tiny = {"n1": 2, "n3": 2, "steps_per_sample": 1, "t2_steps": [0]}
+    P.heom_batch_response_2d(b, rhos, tiny, precision)          # warm-up (code objects)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Rb = P.heom_batch_response_2d(b, rhos, grid, precision)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Rs = [P.heom_response_2d(m, r, grid, precision, "adjoint") for m, r in zip(models, rhos)]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    diff = max(float(np.max(np.abs(a - c)) / max(np.max(np.abs(c)), 1e-300)) for a, c in zip(Rb, Rs))
+    n1, sps = grid["n1"], grid["steps_per_sample"]
+    # single-trajectory RK4 steps: t3 scan (adjoint) + one t1 scan per pathway
+    ado_steps = sum(m.n_ado for m in models) * 3 * (n1 - 1) * sps
+    return {"instances": len(models), "grid": [n1, grid["n3"]], "t2": 0, "precision": precision,
+            "d_classes": sorted({m.d for m in models}),
+            "s_batched": t_batch, "s_one_by_one": t_seq, "speedup": t_seq / t_batch,
+            "ado_updates_per_s_batched": ado_steps / t_batch, "max_rel_diff_vs_one_by_one": diff,
+            "rho_eq": "ground state (timing only)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +138,7 @@ def main():
     ap.add_argument("--spectrum", type=int, default=1, help="also time one full 2D spectrum")
     ap.add_argument("--eq-steps", type=int, default=200)
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--multi", type=int, default=1, help="also time the 64-instance uneven batch")
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "mfma", "mfma_dyn"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -193,6 +230,8 @@ def main():
         line["spectrum_config"] = {"t2": 0, "grid": [g1["n1"], g1["n3"]], "method": "adjoint",
                                    "equilibration_steps": eq_steps, "finite": bool(np.isfinite(S).all())}
     del s
+    if args.multi:
+        line["multi_instance"] = multi_instance(P, torch, args.precision, stream.cuda_stream)
     if args.cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(params)
     print(json.dumps(line))

@@ -224,6 +224,27 @@ int heom_response_2d(heom_model* model, const heom_state* rho_eq, const heom_gri
 int heom_spectrum_2d(const double* R_I, const double* R_II, int n1, int n3, double dt_s,
                      double* S_out);
 
+/* ------------------------------------------- several model instances -- */
+/* A batch of models (instances) of possibly different sizes, propagated
+ * together: every RK4 stage is one persistent matrix-core launch per size
+ * class ceil(d/16), covering the matrices of all instances of that class
+ * (workgroups re-stage H and v_s when they move to another instance).  The
+ * models are borrowed and must outlive the batch; they must share the device,
+ * the stream and the time step, and each needs d <= 112 (FP32) or d <= 80
+ * (FP64).  HEOM_ERR_PARAM otherwise. */
+typedef struct heom_batch heom_batch;
+int heom_batch_create(heom_model* const* models, int n_models, heom_batch** out);
+void heom_batch_free(heom_batch* batch);
+/* n_steps RK4 steps (forward or transposed generator) of states[i] (a state
+ * of models[i]; all states in one precision), batched across instances. */
+int heom_batch_propagate(heom_batch* batch, heom_state* const* states, int n_steps, int adjoint);
+/* Third-order responses of every instance with the adjoint detection method
+ * (see heom_response_2d), all propagations batched across instances.
+ * rho_eq[i]: FP64 one-trajectory state of models[i]; R_out[i]: host
+ * [n_t2][2][n1][n3] complex for instance i. */
+int heom_batch_response_2d(heom_batch* batch, const heom_state* const* rho_eq, const heom_grid* grid,
+                           int precision, double* const* R_out);
+
 /* ------------------------------------------------------ kernel choice -- */
 /* Implementations of the fused RHS / RK4-stage kernel:
  *   HEOM_KERNEL_GENERIC : VALU kernel, one workgroup of 64/256 threads per

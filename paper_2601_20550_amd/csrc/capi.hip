@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -536,6 +537,171 @@ void response_adjoint(heom_model* m, const heom_state* rho_eq, const heom_grid& 
 
 }  // namespace
 
+struct heom_batch {
+  std::vector<heom_model*> models;
+  hipStream_t stream = nullptr;
+  double dt = 0.0;
+};
+
+namespace {
+
+// Descriptor sets of one batched propagation: per size class and for both
+// generators, the four stage role assignments of the Horner RK4 step.
+template <typename T>
+struct BatchProp {
+  struct Class {
+    int nb = 0, vw = 1, n_inst = 0;
+    long long n_items = 0;
+    DevBuf desc[2][4];
+  };
+  std::vector<Class> classes;
+  std::vector<DevBuf> w1, w2;
+
+  void build(heom_batch* b, const std::vector<T*>& ys, const std::vector<int>& n_traj) {
+    const int n = static_cast<int>(b->models.size());
+    std::map<int, std::vector<int>> by_nb;
+    for (int i = 0; i < n; ++i) by_nb[(b->models[i]->hm.d + 15) / 16].push_back(i);
+    w1.clear();
+    w2.clear();
+    w1.resize(n);
+    w2.resize(n);
+    for (int i = 0; i < n; ++i) {
+      const size_t bytes = static_cast<size_t>(n_traj[i]) * b->models[i]->traj_elems() * sizeof(T);
+      w1[i] = DevBuf(bytes);
+      w2[i] = DevBuf(bytes);
+    }
+    classes.clear();
+    for (auto& kv : by_nb) {
+      Class c;
+      c.nb = kv.first;
+      c.n_inst = static_cast<int>(kv.second.size());
+      const int full_vw = 16 / static_cast<int>(sizeof(T));
+      c.vw = full_vw;
+      for (int i : kv.second)
+        if (b->models[i]->hm.d % full_vw) c.vw = 1;
+      for (int a = 0; a < 2; ++a)
+        for (int st = 0; st < 4; ++st) {
+          std::vector<heom::InstDesc<T>> h;
+          long long begin = 0;
+          for (int i : kv.second) {
+            heom_model* m = b->models[i];
+            T* y = ys[i];
+            T* p1 = w1[i].as<T>();
+            T* p2 = w2[i].as<T>();
+            heom::InstDesc<T> d;
+            d.op = ops_of<T>(m, a == 1);
+            d.Hp = padded_H<T>(m);
+            const T* ins[4] = {y, p1, p2, p1};
+            T* outs[4] = {p1, p2, p1, y};
+            d.in = ins[st];
+            d.y = y;
+            d.out = outs[st];
+            d.item_begin = begin;
+            begin += static_cast<long long>(n_traj[i]) * m->hm.n_ado;
+            h.push_back(d);
+          }
+          c.n_items = begin;
+          c.desc[a][st] = upload_vec(h, b->stream);
+        }
+      classes.push_back(std::move(c));
+    }
+  }
+
+  void steps(heom_batch* b, int n_steps, bool adjoint) {
+    const double h = b->dt;
+    const double coef[4] = {h / 4.0, h / 3.0, h / 2.0, h};
+    for (int k = 0; k < n_steps; ++k)
+      for (int st = 0; st < 4; ++st)
+        for (auto& c : classes)
+          heom::launch_rhs_mfma_multi<T>(c.desc[adjoint ? 1 : 0][st].template as<heom::InstDesc<T>>(), c.n_inst,
+                                         c.nb, c.vw, coef[st], c.n_items, b->stream);
+  }
+};
+
+template <typename T>
+void batch_response_adjoint(heom_batch* b, const heom_state* const* rho_eq, const heom_grid& g,
+                            double* const* R_out) {
+  const int n = static_cast<int>(b->models.size());
+  const int n1 = g.n1, n3 = g.n3, sps = g.steps_per_sample;
+  std::vector<long long> te(n);
+  for (int i = 0; i < n; ++i) te[i] = b->models[i]->traj_elems();
+  // detection functionals l_i (mu^T on ADO 0) and Psi_i[k] = (mu+^x)^T l_i(t3_k)
+  std::vector<DevBuf> l(n), Psi(n), X(n), snap(n), tmp64(n), Rdev(n);
+  size_t work_doubles = 0;
+  for (int i = 0; i < n; ++i) {
+    heom_model* m = b->models[i];
+    const int d = m->hm.d;
+    std::vector<double> h(static_cast<size_t>(te[i]), 0.0);
+    for (int a = 0; a < d; ++a)
+      for (int c = 0; c < d; ++c) h[static_cast<size_t>(a) * d + c] = m->hm.mu[static_cast<size_t>(c) * d + a];
+    DevBuf l64 = upload_vec(h, b->stream);
+    l[i] = DevBuf(static_cast<size_t>(te[i]) * sizeof(T));
+    heom::launch_convert<double, T>(l64.as<double>(), l[i].as<T>(), te[i], b->stream);
+    hip_check(hipStreamSynchronize(b->stream), "sync");
+    Psi[i] = DevBuf(static_cast<size_t>(n3) * te[i] * sizeof(T));
+    X[i] = DevBuf(static_cast<size_t>(te[i]) * sizeof(T));
+    snap[i] = DevBuf(static_cast<size_t>(n1) * te[i] * sizeof(T));
+    tmp64[i] = DevBuf(static_cast<size_t>(te[i]) * sizeof(double));
+    Rdev[i] = DevBuf(static_cast<size_t>(g.n_t2) * 2 * n1 * n3 * 2 * sizeof(double));
+    work_doubles = std::max(work_doubles, heom::pair_work_doubles(n1, n3, m->hm.n_ado, d));
+  }
+  DevBuf work(work_doubles * sizeof(double));
+  {
+    BatchProp<T> pl;
+    std::vector<T*> ys(n);
+    for (int i = 0; i < n; ++i) ys[i] = l[i].as<T>();
+    pl.build(b, ys, std::vector<int>(n, 1));
+    for (int k = 0; k < n3; ++k) {
+      if (k) pl.steps(b, sps, true);
+      for (int i = 0; i < n; ++i)
+        heom::launch_commutator<T>(b->models[i]->mu64[HEOM_OP_MU_PLUS].as<double>(), 1, l[i].as<T>(),
+                                   Psi[i].as<T>() + k * te[i], b->models[i]->hm.d, b->models[i]->hm.n_ado,
+                                   b->stream);
+    }
+  }
+  BatchProp<T> px, py;
+  {
+    std::vector<T*> ys(n);
+    for (int i = 0; i < n; ++i) ys[i] = X[i].as<T>();
+    px.build(b, ys, std::vector<int>(n, 1));
+    if (g.t2_steps[g.n_t2 - 1] > 0) {
+      for (int i = 0; i < n; ++i) ys[i] = snap[i].as<T>();
+      py.build(b, ys, std::vector<int>(n, n1));
+    }
+  }
+  const int pw_d[2][2] = {{HEOM_OP_MU_MINUS, HEOM_OP_MU_PLUS}, {HEOM_OP_MU_PLUS, HEOM_OP_MU_MINUS}};
+  for (int P = 0; P < 2; ++P) {
+    for (int i = 0; i < n; ++i)
+      commute_from64<T>(b->models[i], pw_d[P][0], 0, rho_eq[i]->buf.as<double>(), X[i].as<T>(),
+                        b->models[i]->hm.n_ado, tmp64[i].as<double>());
+    for (int j = 0; j < n1; ++j) {
+      if (j) px.steps(b, sps, false);
+      for (int i = 0; i < n; ++i)
+        heom::launch_commutator<T>(b->models[i]->mu64[pw_d[P][1]].as<double>(), 0, X[i].as<T>(),
+                                   snap[i].as<T>() + j * te[i], b->models[i]->hm.d, b->models[i]->hm.n_ado,
+                                   b->stream);
+    }
+    int done = 0;
+    for (int q = 0; q < g.n_t2; ++q) {
+      if (g.t2_steps[q] > done) py.steps(b, g.t2_steps[q] - done, false);
+      done = g.t2_steps[q];
+      for (int i = 0; i < n; ++i) {
+        heom_model* m = b->models[i];
+        double* out = Rdev[i].as<double>() + 2 * ((static_cast<long long>(q) * 2 + P) * n1 * n3);
+        heom::launch_pairing<T>(snap[i].as<T>(), n1, Psi[i].as<T>(), n3, m->hm.n_ado, m->hm.d, 0.0, -1.0,
+                                work.as<double>(), out, b->stream);
+      }
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    check_finite<T>(b->models[i], snap[i].as<T>(), n1, "batched propagation");
+    hip_check(hipMemcpyAsync(R_out[i], Rdev[i].p, Rdev[i].bytes, hipMemcpyDeviceToHost, b->stream), "copy");
+  }
+  hip_check(hipStreamSynchronize(b->stream), "sync");
+}
+
+}  // namespace
+
 // ============================================================== C ABI =====
 
 extern "C" {
@@ -958,6 +1124,119 @@ int heom_spectrum_2d(const double* R_I, const double* R_II, int n1, int n3, doub
     heom::launch_spectrum(dI.as<double>(), dII.as<double>(), n1, n3, dt_s, work.as<double>(), S.as<double>(),
                           nullptr);
     hip_check(hipMemcpy(S_out, S.p, S.bytes, hipMemcpyDeviceToHost), "download");
+  });
+}
+
+int heom_batch_create(heom_model* const* models, int n_models, heom_batch** out) {
+  return guarded([&] {
+    if (!out || !models || n_models < 1) throw HeomError(HEOM_ERR_PARAM, "bad batch arguments");
+    *out = nullptr;
+    auto b = std::make_unique<heom_batch>();
+    for (int i = 0; i < n_models; ++i) {
+      heom_model* m = models[i];
+      require_device(m);
+      if (i == 0) {
+        b->stream = m->stream;
+        b->dt = m->hm.dt;
+      } else {
+        if (m->stream != b->stream) throw HeomError(HEOM_ERR_PARAM, "batch models must share the stream");
+        if (m->hm.dt != b->dt) throw HeomError(HEOM_ERR_PARAM, "batch models must share the time step");
+        if (m->device != models[0]->device) throw HeomError(HEOM_ERR_PARAM, "batch models must share the device");
+      }
+      if (!heom::mfma_supported<float>(m->hm.d) || (m->hm.d + 15) / 16 > 7)
+        throw HeomError(HEOM_ERR_PARAM, "batch model dimension too large for the matrix-core kernel");
+      b->models.push_back(m);
+    }
+    *out = b.release();
+  });
+}
+
+void heom_batch_free(heom_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  delete b;
+}
+
+int heom_batch_propagate(heom_batch* b, heom_state* const* states, int n_steps, int adjoint) {
+  return guarded([&] {
+    if (!b || !states || n_steps < 0) throw HeomError(HEOM_ERR_PARAM, "bad arguments");
+    const int n = static_cast<int>(b->models.size());
+    const int prec = states[0] ? states[0]->precision : -1;
+    std::vector<int> nt(n);
+    for (int i = 0; i < n; ++i) {
+      require_state(b->models[i], states[i]);
+      if (states[i]->precision != prec) throw HeomError(HEOM_ERR_STATE, "batch states must share the precision");
+      nt[i] = states[i]->n_traj;
+    }
+    if (prec == HEOM_FP64) {
+      for (auto* m : b->models)
+        if (!heom::mfma_supported<double>(m->hm.d)) throw HeomError(HEOM_ERR_PARAM, "FP64 batch needs d <= 80");
+      BatchProp<double> bp;
+      std::vector<double*> ys(n);
+      for (int i = 0; i < n; ++i) ys[i] = states[i]->buf.as<double>();
+      bp.build(b, ys, nt);
+      bp.steps(b, n_steps, adjoint != 0);
+      for (int i = 0; i < n; ++i) check_finite<double>(b->models[i], ys[i], nt[i], "batched propagation");
+    } else {
+      BatchProp<float> bp;
+      std::vector<float*> ys(n);
+      for (int i = 0; i < n; ++i) ys[i] = states[i]->buf.as<float>();
+      bp.build(b, ys, nt);
+      bp.steps(b, n_steps, adjoint != 0);
+      for (int i = 0; i < n; ++i) check_finite<float>(b->models[i], ys[i], nt[i], "batched propagation");
+    }
+  });
+}
+
+int heom_batch_response_2d(heom_batch* b, const heom_state* const* rho_eq, const heom_grid* grid, int precision,
+                           double* const* R_out) {
+  return guarded([&] {
+    if (!b || !rho_eq || !grid || !R_out) throw HeomError(HEOM_ERR_PARAM, "null argument");
+    const heom_grid& g = *grid;
+    if (g.n1 < 1 || g.n3 < 1 || g.steps_per_sample < 1 || g.n_t2 < 1 || !g.t2_steps)
+      throw HeomError(HEOM_ERR_PARAM, "bad grid");
+    for (int i = 0; i < g.n_t2; ++i)
+      if (g.t2_steps[i] < 0 || (i && g.t2_steps[i] < g.t2_steps[i - 1]))
+        throw HeomError(HEOM_ERR_PARAM, "t2_steps must be non-negative and non-decreasing");
+    for (size_t i = 0; i < b->models.size(); ++i) {
+      require_state(b->models[i], rho_eq[i]);
+      if (rho_eq[i]->precision != HEOM_FP64 || rho_eq[i]->n_traj != 1)
+        throw HeomError(HEOM_ERR_STATE, "rho_eq must be FP64 states with one trajectory");
+      if (!R_out[i]) throw HeomError(HEOM_ERR_PARAM, "null output");
+    }
+    if (precision != HEOM_FP64 && precision != HEOM_FP32) throw HeomError(HEOM_ERR_PARAM, "bad precision");
+    if (precision == HEOM_FP64)
+      for (auto* m : b->models)
+        if (!heom::mfma_supported<double>(m->hm.d)) throw HeomError(HEOM_ERR_PARAM, "FP64 batch needs d <= 80");
+    // Instances go in groups whose buffers (Psi: n3, snapshots: n1, their two
+    // RK4 scratch copies when t2 > 0, a few single states) fit in free memory.
+    const size_t elem = precision == HEOM_FP64 ? sizeof(double) : sizeof(float);
+    const bool any_t2 = g.t2_steps[g.n_t2 - 1] > 0;
+    const size_t fr = free_device_bytes();
+    const size_t budget = fr > (size_t(2) << 30) ? fr - (size_t(2) << 30) : 0;
+    const int n = static_cast<int>(b->models.size());
+    int i0 = 0;
+    while (i0 < n) {
+      size_t used = 0;
+      int i1 = i0;
+      while (i1 < n) {
+        const size_t te = static_cast<size_t>(b->models[i1]->traj_elems());
+        const size_t need = te * (elem * (g.n1 + g.n3 + (any_t2 ? 2 * g.n1 : 0) + 4) + 2 * sizeof(double));
+        if (i1 > i0 && used + need > budget) break;
+        used += need;
+        ++i1;
+      }
+      if (used > budget) throw HeomError(HEOM_ERR_OOM, "not enough device memory for one instance");
+      heom_batch sub;
+      sub.models.assign(b->models.begin() + i0, b->models.begin() + i1);
+      sub.stream = b->stream;
+      sub.dt = b->dt;
+      if (precision == HEOM_FP64)
+        batch_response_adjoint<double>(&sub, rho_eq + i0, g, R_out + i0);
+      else
+        batch_response_adjoint<float>(&sub, rho_eq + i0, g, R_out + i0);
+      i0 = i1;
+    }
   });
 }
 

@@ -41,6 +41,28 @@ template <typename T>
 void launch_rhs_mfma(const DevOps<T>& op, const T* Hp, const T* in, const T* y, T* out, double coef,
                      int n_traj, int variant, hipStream_t stream);
 
+// One model instance inside a multi-instance launch (see
+// launch_rhs_mfma_multi): its tables, its padded H, the input, base (y, may be
+// null) and output hierarchies of its n_traj trajectories, and its first item
+// in the launch (items of an instance: n_traj x n_ado).
+template <typename T>
+struct InstDesc {
+  DevOps<T> op;
+  const T* Hp;
+  const T* in;
+  const T* y;
+  T* out;
+  long long item_begin;
+};
+
+// Matrix-core RHS / RK4 stage over several instances of one size class
+// (nb = ceil(d/16) equal for all) in one persistent launch.  desc: device
+// array of n_inst descriptors sorted by item_begin; vw = 16 / sizeof(T) if
+// every instance has d divisible by it, else 1.
+template <typename T>
+void launch_rhs_mfma_multi(const InstDesc<T>* desc, int n_inst, int nb, int vw, double coef, long long n_items,
+                           hipStream_t stream);
+
 // dst = D^x src (or (D^T)^x src) on every ADO, FP64 arithmetic.
 template <typename T>
 void launch_commutator(const double* D, int transpose, const T* src, T* dst, int d,

@@ -136,35 +136,13 @@ __device__ inline void vset(typename Vec<T, VW>::type& v, int i, T x) {
   }
 }
 
-template <typename T, int NB, typename Shape, int MINW, int VW>
-__global__ __launch_bounds__(NB * 64, MINW) void rhs_mfma_kernel(DevOps<T> op, const T* __restrict__ Hp,
-                                                                 const T* __restrict__ in, const T* y, T* out,
-                                                                 T coef, long long n_items) {
+// Stages H (zero padded to DP x DP), the single-mode operators v_s and zero
+// padding of the rho planes into LDS.
+template <typename T, int NB, typename Shape>
+__device__ inline void stage_operators(const DevOps<T>& op, const Shape& sh, const T* __restrict__ Hp, T* sRe,
+                                       T* sH, T* sV) {
   using L = Lds<T, NB>;
-  using M = Mfma<T>;
-  using acc_t = typename M::acc;
-  using vec_t = typename Vec<T, VW>::type;
-  constexpr int DP = L::DP, LD = L::LD;
-  constexpr int NT = NB * 64;
-  // vectors per lane covering a 16-row block of DP columns
-  constexpr int RV = (16 * DP + VW * 64 - 1) / (VW * 64);
-  extern __shared__ unsigned char smem_raw[];
-  T* sRe = reinterpret_cast<T*>(smem_raw);
-  T* sIm = sRe + L::PLANE;
-  T* sH = sRe + L::HOFF;
-  T* sV = sRe + L::VOFF;
-
-  const Shape sh(op.dims, op.strides, op.n_modes, op.d);
-  const int d = sh.d();
-  const long long dd = static_cast<long long>(d) * d;
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int rows0 = 16 * wave;
-  // elements of this wave's row block (rows rows0 .. rows0+15, clipped to d)
-  const int rb_rows = rows0 < d ? (d - rows0 < 16 ? d - rows0 : 16) : 0;
-  const int rb_elems = rb_rows * d;
-
-  // once per workgroup: H (padded) and v_s into LDS
+  constexpr int DP = L::DP, LD = L::LD, NT = NB * 64;
   for (int e = threadIdx.x; e < DP * DP; e += NT) {
     const int r = e / DP, c = e - (e / DP) * DP;
     sH[r * LD + c] = Hp[e];
@@ -175,244 +153,314 @@ __global__ __launch_bounds__(NB * 64, MINW) void rhs_mfma_kernel(DevOps<T> op, c
     const int ds2 = sh.dim(s) * sh.dim(s);
     for (int e = threadIdx.x; e < ds2; e += NT) sV[s * 64 + e] = op.v[op.v_off[s] + e];
   }
-  // zero the padding rows/columns of the rho planes once; only the d x d
-  // block is rewritten per item
+  // only the d x d block of the rho planes is rewritten per matrix
   for (int e = threadIdx.x; e < 2 * L::PLANE; e += NT) sRe[e] = T(0);
+}
 
-  for (long long item = blockIdx.x; item < n_items; item += gridDim.x) {
-    // Per-lane index arithmetic is redone for every item: an opaque copy of
-    // the lane id keeps the compiler from hoisting hundreds of LDS addresses
-    // of the unrolled loops out of the item loop (register pressure).
-    int lane_v = lane;
-    asm volatile("" : "+v"(lane_v));
-    const int lr = lane_v & 15;
-    const int lq = lane_v >> 4;
-    const int n = static_cast<int>(item % op.n_ado);
-    const long long base = item * 2 * dd;
-    const long long traj_base = (item - n) * 2 * dd;
-    const T* rin = in + base;
+// out = y + coef * L(in) (y may be null: out = L(in)) for matrix `item` of a
+// hierarchy batch whose trajectories start at `in`, `y`, `out`; H and v_s are
+// already in LDS.
+template <typename T, int NB, typename Shape, int VW>
+__device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, const T* __restrict__ in,
+                                         const T* y, T* out, T coef, long long item, T* sRe, T* sIm,
+                                         const T* sH, const T* sV) {
+  using L = Lds<T, NB>;
+  using M = Mfma<T>;
+  using acc_t = typename M::acc;
+  using vec_t = typename Vec<T, VW>::type;
+  constexpr int DP = L::DP, LD = L::LD;
+  constexpr int NT = NB * 64;
+  // vectors per lane covering a 16-row block of DP columns
+  constexpr int RV = (16 * DP + VW * 64 - 1) / (VW * 64);
+  const int d = sh.d();
+  const long long dd = static_cast<long long>(d) * d;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int rows0 = 16 * wave;
+  // elements of this wave's row block (rows rows0 .. rows0+15, clipped to d)
+  const int rb_rows = rows0 < d ? (d - rows0 < 16 ? d - rows0 : 16) : 0;
+  const int rb_elems = rb_rows * d;
+  (void)DP;
+  // Per-lane index arithmetic is redone for every item: an opaque copy of
+  // the lane id keeps the compiler from hoisting hundreds of LDS addresses
+  // of the unrolled loops out of the item loop (register pressure).
+  int lane_v = lane;
+  asm volatile("" : "+v"(lane_v));
+  const int lr = lane_v & 15;
+  const int lq = lane_v >> 4;
+  const int n = static_cast<int>(item % op.n_ado);
+  const long long base = item * 2 * dd;
+  const long long traj_base = (item - n) * 2 * dd;
+  const T* rin = in + base;
 
-    __syncthreads();  // previous item's LDS reads are complete
-    // ---- stage rho_n: 16-byte loads, d x d block of the LDS planes -------
-    for (int v = threadIdx.x; v * VW < dd; v += NT) {
-      const vec_t xr = *reinterpret_cast<const vec_t*>(rin + static_cast<long long>(v) * VW);
-      const vec_t xi = *reinterpret_cast<const vec_t*>(rin + dd + static_cast<long long>(v) * VW);
-      const int e = v * VW, r = e / d, c = e - (e / d) * d;
+  __syncthreads();  // previous item's LDS reads are complete
+  // ---- stage rho_n: 16-byte loads, d x d block of the LDS planes -------
+  for (int v = threadIdx.x; v * VW < dd; v += NT) {
+    const vec_t xr = *reinterpret_cast<const vec_t*>(rin + static_cast<long long>(v) * VW);
+    const vec_t xi = *reinterpret_cast<const vec_t*>(rin + dd + static_cast<long long>(v) * VW);
+    const int e = v * VW, r = e / d, c = e - (e / d) * d;
 #pragma unroll
-      for (int i = 0; i < VW; ++i) {
-        sRe[r * LD + c + i] = vget<T, VW>(xr, i);
-        sIm[r * LD + c + i] = vget<T, VW>(xi, i);
-      }
+    for (int i = 0; i < VW; ++i) {
+      sRe[r * LD + c + i] = vget<T, VW>(xr, i);
+      sIm[r * LD + c + i] = vget<T, VW>(xi, i);
     }
-    __syncthreads();
+  }
+  __syncthreads();
 
-    // ---- H commutator of row block w --------------------------------------
-    //   Re L += H Im - Im H,   Im L += Re H - H Re
-    acc_t Rre[NB], Rim[NB];
+  // ---- H commutator of row block w --------------------------------------
+  //   Re L += H Im - Im H,   Im L += Re H - H Re
+  acc_t Rre[NB], Rim[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    Rre[j] = acc_t{0, 0, 0, 0};
+    Rim[j] = acc_t{0, 0, 0, 0};
+  }
+#pragma unroll
+  for (int kk = 0; kk < 4 * NB; ++kk) {
+    const int k = 4 * kk + lq;
+    const T hA = sH[(rows0 + lr) * LD + k];
+    const T nhA = -hA;
+    const T aRe = sRe[(rows0 + lr) * LD + k];
+    const T naIm = -sIm[(rows0 + lr) * LD + k];
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      Rre[j] = acc_t{0, 0, 0, 0};
-      Rim[j] = acc_t{0, 0, 0, 0};
+      const T hB = sH[k * LD + 16 * j + lr];
+      Rre[j] = M::mma(hA, sIm[k * LD + 16 * j + lr], Rre[j]);
+      Rre[j] = M::mma(naIm, hB, Rre[j]);
+      Rim[j] = M::mma(nhA, sRe[k * LD + 16 * j + lr], Rim[j]);
+      Rim[j] = M::mma(aRe, hB, Rim[j]);
     }
+    // keep the scheduler from hoisting the LDS operands of many k-slices
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // damping
+  const T g = op.gamma[n];
 #pragma unroll
-    for (int kk = 0; kk < 4 * NB; ++kk) {
-      const int k = 4 * kk + lq;
-      const T hA = sH[(rows0 + lr) * LD + k];
-      const T nhA = -hA;
-      const T aRe = sRe[(rows0 + lr) * LD + k];
-      const T naIm = -sIm[(rows0 + lr) * LD + k];
+  for (int j = 0; j < NB; ++j)
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        const T hB = sH[k * LD + 16 * j + lr];
-        Rre[j] = M::mma(hA, sIm[k * LD + 16 * j + lr], Rre[j]);
-        Rre[j] = M::mma(naIm, hB, Rre[j]);
-        Rim[j] = M::mma(nhA, sRe[k * LD + 16 * j + lr], Rim[j]);
-        Rim[j] = M::mma(aRe, hB, Rim[j]);
-      }
-      // keep the scheduler from hoisting the LDS operands of many k-slices
-      __builtin_amdgcn_sched_barrier(0);
+    for (int r = 0; r < 4; ++r) {
+      const int a = rows0 + M::crow(lq, r), c = 16 * j + lr;
+      Rre[j][r] -= g * sRe[a * LD + c];
+      Rim[j][r] -= g * sIm[a * LD + c];
     }
-    // damping
-    const T g = op.gamma[n];
-#pragma unroll
-    for (int j = 0; j < NB; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int a = rows0 + M::crow(lq, r), c = 16 * j + lr;
-        Rre[j][r] -= g * sRe[a * LD + c];
-        Rim[j][r] -= g * sIm[a * LD + c];
-      }
 
-    // ---- couplings to the hierarchy neighbours ----------------------------
-    // X_s is accumulated row block by row block directly in the LDS planes
-    // (each wave updates only its own rows) from 16-byte loads.
+  // ---- couplings to the hierarchy neighbours ----------------------------
+  // X_s is accumulated row block by row block directly in the LDS planes
+  // (each wave updates only its own rows) from 16-byte loads.
 #pragma unroll 1
-    for (int s = 0; s < 4; ++s) {
-      if (s >= sh.nm()) break;
-      const int p0 = op.nb_ptr[n * op.n_modes + s];
-      const int p1 = op.nb_ptr[n * op.n_modes + s + 1];
-      if (p0 == p1) continue;  // uniform across the workgroup
-      const int ds = sh.dim(s), st = sh.stride(s);
-      const T* vs = sV + s * 64;
-      // X_s (and W = sum_q Im(aL_q) rho_q, for Y_s) of this wave's rows in
-      // registers, one 16-byte load per vector and neighbour
-      vec_t xr[RV], xi[RV], wr[RV], wi[RV];
-      bool have_w = false;
+  for (int s = 0; s < 4; ++s) {
+    if (s >= sh.nm()) break;
+    const int p0 = op.nb_ptr[n * op.n_modes + s];
+    const int p1 = op.nb_ptr[n * op.n_modes + s + 1];
+    if (p0 == p1) continue;  // uniform across the workgroup
+    const int ds = sh.dim(s), st = sh.stride(s);
+    const T* vs = sV + s * 64;
+    // X_s (and W = sum_q Im(aL_q) rho_q, for Y_s) of this wave's rows in
+    // registers, one 16-byte load per vector and neighbour
+    vec_t xr[RV], xi[RV], wr[RV], wi[RV];
+    bool have_w = false;
+#pragma unroll
+    for (int k = 0; k < RV; ++k) {
+#pragma unroll
+      for (int i = 0; i < VW; ++i) {
+        vset<T, VW>(xr[k], i, T(0));
+        vset<T, VW>(xi[k], i, T(0));
+        vset<T, VW>(wr[k], i, T(0));
+        vset<T, VW>(wi[k], i, T(0));
+      }
+    }
+    for (int q = p0; q < p1; ++q) {
+      const T* rm = in + traj_base + static_cast<long long>(op.nb_idx[q]) * 2 * dd + rows0 * d;
+      const T ar = op.nb_a[4 * q], ai = op.nb_a[4 * q + 1];
+      const bool cplx = ai != T(0);
+      have_w = have_w || cplx;
 #pragma unroll
       for (int k = 0; k < RV; ++k) {
+        const int e = (lane + 64 * k) * VW;
+        if (e < rb_elems) {
+          const vec_t br = *reinterpret_cast<const vec_t*>(rm + e);
+          const vec_t bi = *reinterpret_cast<const vec_t*>(rm + dd + e);
+          xr[k] += ar * br - ai * bi;
+          xi[k] += ar * bi + ai * br;
+          if (cplx) {
+            wr[k] += ai * br;
+            wi[k] += ai * bi;
+          }
+        }
+      }
+    }
+    __syncthreads();  // every wave is done with the previous LDS content
+#pragma unroll
+    for (int k = 0; k < RV; ++k) {
+      const int e = (lane + 64 * k) * VW;
+      if (e < rb_elems) {
+        const int r = rows0 + e / d, c = e - (e / d) * d;
 #pragma unroll
         for (int i = 0; i < VW; ++i) {
-          vset<T, VW>(xr[k], i, T(0));
-          vset<T, VW>(xi[k], i, T(0));
-          vset<T, VW>(wr[k], i, T(0));
-          vset<T, VW>(wi[k], i, T(0));
-        }
-      }
-      for (int q = p0; q < p1; ++q) {
-        const T* rm = in + traj_base + static_cast<long long>(op.nb_idx[q]) * 2 * dd + rows0 * d;
-        const T ar = op.nb_a[4 * q], ai = op.nb_a[4 * q + 1];
-        const bool cplx = ai != T(0);
-        have_w = have_w || cplx;
-#pragma unroll
-        for (int k = 0; k < RV; ++k) {
-          const int e = (lane + 64 * k) * VW;
-          if (e < rb_elems) {
-            const vec_t br = *reinterpret_cast<const vec_t*>(rm + e);
-            const vec_t bi = *reinterpret_cast<const vec_t*>(rm + dd + e);
-            xr[k] += ar * br - ai * bi;
-            xi[k] += ar * bi + ai * br;
-            if (cplx) {
-              wr[k] += ai * br;
-              wi[k] += ai * bi;
-            }
-          }
-        }
-      }
-      __syncthreads();  // every wave is done with the previous LDS content
-#pragma unroll
-      for (int k = 0; k < RV; ++k) {
-        const int e = (lane + 64 * k) * VW;
-        if (e < rb_elems) {
-          const int r = rows0 + e / d, c = e - (e / d) * d;
-#pragma unroll
-          for (int i = 0; i < VW; ++i) {
-            sRe[r * LD + c + i] = vget<T, VW>(xr[k], i);
-            sIm[r * LD + c + i] = vget<T, VW>(xi[k], i);
-          }
-        }
-      }
-      __syncthreads();
-      // left product: (V_s X_s)[a][c] = sum_k v_s[a_s][k] X_s[a + (k - a_s) st][c];  L += -i V X
-      {
-        int as[4], r0[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int a = rows0 + M::crow(lq, r);
-          as[r] = (a / st) % ds;
-          r0[r] = a - as[r] * st;
-        }
-        for (int k = 0; k < ds; ++k) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const T v = vs[as[r] * ds + k];
-            const int rowoff = (r0[r] + k * st) * LD + lr;
-#pragma unroll
-            for (int j = 0; j < NB; ++j) {
-              Rre[j][r] += v * sIm[rowoff + 16 * j];
-              Rim[j][r] -= v * sRe[rowoff + 16 * j];
-            }
-          }
-        }
-      }
-      __syncthreads();  // left products read other waves' rows
-      // Y_s = X_s - 2i W on this wave's rows
-      if (have_w) {
-#pragma unroll
-        for (int k = 0; k < RV; ++k) {
-          const int e = (lane + 64 * k) * VW;
-          if (e < rb_elems) {
-            const int r = rows0 + e / d, c = e - (e / d) * d;
-#pragma unroll
-            for (int i = 0; i < VW; ++i) {
-              sRe[r * LD + c + i] = vget<T, VW>(xr[k], i) + 2 * vget<T, VW>(wi[k], i);
-              sIm[r * LD + c + i] = vget<T, VW>(xi[k], i) - 2 * vget<T, VW>(wr[k], i);
-            }
-          }
-        }
-      }
-      __syncthreads();
-      // right product: (Y_s V_s)[a][c] = sum_k Y_s[a][c + (k - c_s) st] v_s[k][c_s];  L += i Y V
-      {
-        int cs[NB], c0[NB];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          const int c = 16 * j + lr;
-          cs[j] = (c / st) % ds;
-          c0[j] = c - cs[j] * st;
-        }
-        for (int k = 0; k < ds; ++k) {
-#pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            const T v = vs[k * ds + cs[j]];
-            const int coloff = c0[j] + k * st;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int a = rows0 + M::crow(lq, r);
-              Rre[j][r] -= v * sIm[a * LD + coloff];
-              Rim[j][r] += v * sRe[a * LD + coloff];
-            }
-          }
+          sRe[r * LD + c + i] = vget<T, VW>(xr[k], i);
+          sIm[r * LD + c + i] = vget<T, VW>(xi[k], i);
         }
       }
     }
-
-    // ---- epilogue: out = y + coef * L ---------------------------------------
-    // transpose this wave's rows through LDS so that y and out move in
-    // 16-byte vectors
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < NB; ++j)
+    // left product: (V_s X_s)[a][c] = sum_k v_s[a_s][k] X_s[a + (k - a_s) st][c];  L += -i V X
+    {
+      int as[4], r0[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int a = rows0 + M::crow(lq, r), c = 16 * j + lr;
-        sRe[a * LD + c] = Rre[j][r];
-        sIm[a * LD + c] = Rim[j][r];
+        const int a = rows0 + M::crow(lq, r);
+        as[r] = (a / st) % ds;
+        r0[r] = a - as[r] * st;
       }
-    __syncthreads();
-    {
-      const long long ob = base + rows0 * d;
-      vec_t yr[RV], yi[RV];
-      if (y) {
+      for (int k = 0; k < ds; ++k) {
 #pragma unroll
-        for (int k = 0; k < RV; ++k) {
-          const int e = (lane + 64 * k) * VW;
-          if (e < rb_elems) {
-            yr[k] = *reinterpret_cast<const vec_t*>(y + ob + e);
-            yi[k] = *reinterpret_cast<const vec_t*>(y + ob + dd + e);
+        for (int r = 0; r < 4; ++r) {
+          const T v = vs[as[r] * ds + k];
+          const int rowoff = (r0[r] + k * st) * LD + lr;
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            Rre[j][r] += v * sIm[rowoff + 16 * j];
+            Rim[j][r] -= v * sRe[rowoff + 16 * j];
           }
         }
       }
+    }
+    __syncthreads();  // left products read other waves' rows
+    // Y_s = X_s - 2i W on this wave's rows
+    if (have_w) {
 #pragma unroll
       for (int k = 0; k < RV; ++k) {
         const int e = (lane + 64 * k) * VW;
         if (e < rb_elems) {
           const int r = rows0 + e / d, c = e - (e / d) * d;
-          vec_t orr, oi;
 #pragma unroll
           for (int i = 0; i < VW; ++i) {
-            T lre = sRe[r * LD + c + i], lim = sIm[r * LD + c + i];
-            if (y) {
-              lre = vget<T, VW>(yr[k], i) + coef * lre;
-              lim = vget<T, VW>(yi[k], i) + coef * lim;
-            }
-            vset<T, VW>(orr, i, lre);
-            vset<T, VW>(oi, i, lim);
+            sRe[r * LD + c + i] = vget<T, VW>(xr[k], i) + 2 * vget<T, VW>(wi[k], i);
+            sIm[r * LD + c + i] = vget<T, VW>(xi[k], i) - 2 * vget<T, VW>(wr[k], i);
           }
-          *reinterpret_cast<vec_t*>(out + ob + e) = orr;
-          *reinterpret_cast<vec_t*>(out + ob + dd + e) = oi;
         }
       }
     }
+    __syncthreads();
+    // right product: (Y_s V_s)[a][c] = sum_k Y_s[a][c + (k - c_s) st] v_s[k][c_s];  L += i Y V
+    {
+      int cs[NB], c0[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int c = 16 * j + lr;
+        cs[j] = (c / st) % ds;
+        c0[j] = c - cs[j] * st;
+      }
+      for (int k = 0; k < ds; ++k) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const T v = vs[k * ds + cs[j]];
+          const int coloff = c0[j] + k * st;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int a = rows0 + M::crow(lq, r);
+            Rre[j][r] -= v * sIm[a * LD + coloff];
+            Rim[j][r] += v * sRe[a * LD + coloff];
+          }
+        }
+      }
+    }
+  }
+
+  // ---- epilogue: out = y + coef * L ---------------------------------------
+  // transpose this wave's rows through LDS so that y and out move in
+  // 16-byte vectors
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int a = rows0 + M::crow(lq, r), c = 16 * j + lr;
+      sRe[a * LD + c] = Rre[j][r];
+      sIm[a * LD + c] = Rim[j][r];
+    }
+  __syncthreads();
+  {
+    const long long ob = base + rows0 * d;
+    vec_t yr[RV], yi[RV];
+    if (y) {
+#pragma unroll
+      for (int k = 0; k < RV; ++k) {
+        const int e = (lane + 64 * k) * VW;
+        if (e < rb_elems) {
+          yr[k] = *reinterpret_cast<const vec_t*>(y + ob + e);
+          yi[k] = *reinterpret_cast<const vec_t*>(y + ob + dd + e);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < RV; ++k) {
+      const int e = (lane + 64 * k) * VW;
+      if (e < rb_elems) {
+        const int r = rows0 + e / d, c = e - (e / d) * d;
+        vec_t orr, oi;
+#pragma unroll
+        for (int i = 0; i < VW; ++i) {
+          T lre = sRe[r * LD + c + i], lim = sIm[r * LD + c + i];
+          if (y) {
+            lre = vget<T, VW>(yr[k], i) + coef * lre;
+            lim = vget<T, VW>(yi[k], i) + coef * lim;
+          }
+          vset<T, VW>(orr, i, lre);
+          vset<T, VW>(oi, i, lim);
+        }
+        *reinterpret_cast<vec_t*>(out + ob + e) = orr;
+        *reinterpret_cast<vec_t*>(out + ob + dd + e) = oi;
+      }
+    }
+  }
+}
+
+template <typename T, int NB, typename Shape, int MINW, int VW>
+__global__ __launch_bounds__(NB * 64, MINW) void rhs_mfma_kernel(DevOps<T> op, const T* __restrict__ Hp,
+                                                                 const T* __restrict__ in, const T* y, T* out,
+                                                                 T coef, long long n_items) {
+  using L = Lds<T, NB>;
+  extern __shared__ unsigned char smem_raw[];
+  T* sRe = reinterpret_cast<T*>(smem_raw);
+  T* sIm = sRe + L::PLANE;
+  T* sH = sRe + L::HOFF;
+  T* sV = sRe + L::VOFF;
+  const Shape sh(op.dims, op.strides, op.n_modes, op.d);
+  stage_operators<T, NB, Shape>(op, sh, Hp, sRe, sH, sV);
+  for (long long item = blockIdx.x; item < n_items; item += gridDim.x)
+    rhs_item<T, NB, Shape, VW>(op, sh, in, y, out, coef, item, sRe, sIm, sH, sV);
+}
+
+// Several model instances of one size class (same ceil(d/16)) in one
+// persistent launch.  Instance i owns items [desc[i].item_begin,
+// desc[i+1].item_begin).  A workgroup re-stages H and v_s whenever the
+// instance of its next item differs from the previous one.
+template <typename T, int NB, int MINW, int VW>
+__global__ __launch_bounds__(NB * 64, MINW) void rhs_mfma_multi_kernel(const InstDesc<T>* __restrict__ desc,
+                                                                       int n_inst, T coef, long long n_items) {
+  using L = Lds<T, NB>;
+  extern __shared__ unsigned char smem_raw[];
+  T* sRe = reinterpret_cast<T*>(smem_raw);
+  T* sIm = sRe + L::PLANE;
+  T* sH = sRe + L::HOFF;
+  T* sV = sRe + L::VOFF;
+  int cur = -1;
+  for (long long item = blockIdx.x; item < n_items; item += gridDim.x) {
+    int lo = 0, hi = n_inst - 1;  // last instance with item_begin <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (desc[mid].item_begin <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const InstDesc<T>& di = desc[lo];
+    const DynShape sh(di.op.dims, di.op.strides, di.op.n_modes, di.op.d);
+    if (lo != cur) {
+      __syncthreads();  // previous instance's LDS reads are complete
+      stage_operators<T, NB, DynShape>(di.op, sh, di.Hp, sRe, sH, sV);
+      cur = lo;
+    }
+    rhs_item<T, NB, DynShape, VW>(di.op, sh, di.in, di.y, di.out, coef, item - di.item_begin, sRe, sIm, sH, sV);
   }
 }
 
@@ -511,6 +559,60 @@ void launch_rhs_mfma(const DevOps<T>& op, const T* Hp, const T* in, const T* y, 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw std::runtime_error(std::string("mfma rhs kernel: ") + hipGetErrorString(e));
 }
+
+namespace {
+
+template <typename T, int NB, int VW>
+void launch_multi_nb(const InstDesc<T>* desc, int n_inst, T coef, long long n_items, hipStream_t stream) {
+  const size_t lds = Lds<T, NB>::bytes;
+  constexpr int MINW = (sizeof(T) == 4) ? 2 : 1;
+  auto kern = &rhs_mfma_multi_kernel<T, NB, MINW, VW>;
+  static bool configured = false;
+  if (!configured) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              static_cast<int>(lds));
+    configured = true;
+  }
+  int wg = static_cast<int>((160 * 1024) / lds);
+  if (wg < 1) wg = 1;
+  if (wg > 8) wg = 8;
+  long long grid = static_cast<long long>(cu_count()) * wg;
+  if (grid > n_items) grid = n_items;
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(NB * 64), lds, stream, desc, n_inst, coef,
+                     n_items);
+}
+
+template <typename T, int NB>
+void launch_multi_vw(const InstDesc<T>* desc, int n_inst, int vw, T coef, long long n_items, hipStream_t stream) {
+  if (vw == 16 / static_cast<int>(sizeof(T)))
+    launch_multi_nb<T, NB, 16 / sizeof(T)>(desc, n_inst, coef, n_items, stream);
+  else
+    launch_multi_nb<T, NB, 1>(desc, n_inst, coef, n_items, stream);
+}
+
+}  // namespace
+
+template <typename T>
+void launch_rhs_mfma_multi(const InstDesc<T>* desc, int n_inst, int nb, int vw, double coef, long long n_items,
+                           hipStream_t stream) {
+  if (n_items == 0 || n_inst == 0) return;
+  const T c = static_cast<T>(coef);
+  switch (nb) {
+    case 1: launch_multi_vw<T, 1>(desc, n_inst, vw, c, n_items, stream); break;
+    case 2: launch_multi_vw<T, 2>(desc, n_inst, vw, c, n_items, stream); break;
+    case 3: launch_multi_vw<T, 3>(desc, n_inst, vw, c, n_items, stream); break;
+    case 4: launch_multi_vw<T, 4>(desc, n_inst, vw, c, n_items, stream); break;
+    case 5: launch_multi_vw<T, 5>(desc, n_inst, vw, c, n_items, stream); break;
+    case 6: launch_multi_vw<T, 6>(desc, n_inst, vw, c, n_items, stream); break;
+    case 7: launch_multi_vw<T, 7>(desc, n_inst, vw, c, n_items, stream); break;
+    default: throw std::runtime_error("multi-instance MFMA kernel supports ceil(d/16) <= 7");
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw std::runtime_error(std::string("mfma multi kernel: ") + hipGetErrorString(e));
+}
+
+template void launch_rhs_mfma_multi<float>(const InstDesc<float>*, int, int, int, double, long long, hipStream_t);
+template void launch_rhs_mfma_multi<double>(const InstDesc<double>*, int, int, int, double, long long, hipStream_t);
 
 template bool mfma_supported<float>(int);
 template bool mfma_supported<double>(int);

@@ -110,6 +110,11 @@ _SIGS = {
                                    C.c_int, C.c_int, C.c_void_p]),
     "heom_spectrum_2d": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_double,
                                    C.c_void_p]),
+    "heom_batch_create": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]),
+    "heom_batch_free": (None, [C.c_void_p]),
+    "heom_batch_propagate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int]),
+    "heom_batch_response_2d": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(heom_grid), C.c_int,
+                                         C.c_void_p]),
     "heom_model_set_kernel": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "heom_model_get_kernel": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
     "heom_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int),
@@ -394,6 +399,48 @@ def heom_spectrum_2d(R_I, R_II, dt_s):
     S = np.zeros((2 * n3, 2 * n1))
     _check(load_library().heom_spectrum_2d(_ptr(R_I), _ptr(R_II), n1, n3, float(dt_s), _ptr(S)))
     return S
+
+
+class Batch:
+    """Several models propagated together (one launch per size class and RK4 stage)."""
+
+    def __init__(self, models):
+        self.models = list(models)
+        arr = (C.c_void_p * len(self.models))(*[m.handle.value for m in self.models])
+        h = C.c_void_p()
+        _check(_lib.heom_batch_create(arr, len(self.models), C.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.heom_batch_free(self.handle)
+            self.handle = None
+
+
+def heom_batch_create(models) -> Batch:
+    return Batch(models)
+
+
+def heom_batch_propagate(batch: Batch, states, n_steps: int, adjoint=False):
+    if len(states) != len(batch.models):
+        raise ValueError("one state per batch instance")
+    arr = (C.c_void_p * len(states))(*[s.handle.value for s in states])
+    _check(_lib.heom_batch_propagate(batch.handle, arr, int(n_steps), int(bool(adjoint))))
+
+
+def heom_batch_response_2d(batch: Batch, rho_eqs, grid, precision="fp32"):
+    """List of R[t2][pathway][t1][t3] (complex128), one per instance (adjoint method)."""
+    if len(rho_eqs) != len(batch.models):
+        raise ValueError("one rho_eq per batch instance")
+    t2 = (C.c_int * len(grid["t2_steps"]))(*[int(s) for s in grid["t2_steps"]])
+    g = heom_grid(int(grid["n1"]), int(grid["n3"]), int(grid["steps_per_sample"]),
+                  len(grid["t2_steps"]), t2)
+    n_t2 = len(grid["t2_steps"])
+    outs = [np.zeros(n_t2 * 2 * grid["n1"] * grid["n3"] * 2) for _ in batch.models]
+    rho = (C.c_void_p * len(rho_eqs))(*[r.handle.value for r in rho_eqs])
+    optr = (C.c_void_p * len(outs))(*[o.ctypes.data for o in outs])
+    _check(_lib.heom_batch_response_2d(batch.handle, rho, C.byref(g), _PREC[precision], optr))
+    return [(o[0::2] + 1j * o[1::2]).reshape(n_t2, 2, grid["n1"], grid["n3"]) for o in outs]
 
 
 def heom_model_set_kernel(model, precision, kernel):
