@@ -15,11 +15,15 @@ Modules
     hierarchy  ADO index set and neighbour maps.
     heom       right-hand side, classic RK4, equilibration, dipole
                application, response functions and 2D spectra.
+    gradient   least-squares spectrum-fit objective; its derivatives by
+               central differences (parameter level and operator level) and
+               the adjoint of the spectrum map.
 
 Parity status: every function is pinned by a test in tests/test_oracle_pins.py
-against closed forms, exact invariants or brute force, except the seeded
+or tests/test_oracle_gradient.py against closed forms, exact invariants or
+brute force, except the seeded
 water-like spectra themselves, which the paper does not print (parity
 unpinned beyond the oracle for those end-to-end values).
 """
 
-from . import bath, hierarchy, model, heom  # noqa: F401
+from . import bath, hierarchy, model, heom, gradient  # noqa: F401

@@ -12,6 +12,10 @@ from .configs import (  # noqa: F401
     cfg3,
     cfg4_instances,
     cfg5,
+    cfg5_small,
+    apply_theta,
+    theta_directions,
+    theta_size,
     harmonic_pin,
     fs_to_steps,
     response_grid,

@@ -169,3 +169,79 @@ def harmonic_pin(omega=1.0, zeta=0.1, gamma=0.2, V1=1.0, beta=10.0, K=2,
          "n_basis": 12, "n_keep": n_keep, "K": K}
     return {"modes": [m], "couplings": [], "beta": beta, "depth": depth,
             "decomp": decomp, "dt": dt}
+
+
+def theta_size(params) -> int:
+    """Number of fitted factors: g3 and g4 per mode, then bilinear and Fermi
+    coupling scales, then common V1, V2, zeta and gamma scales."""
+    return 2 * len(params["modes"]) + 6
+
+
+def apply_theta(params, theta):
+    """Parameters with the multiplicative factors theta applied (theta = 1: unchanged)."""
+    import copy
+    n = len(params["modes"])
+    theta = [float(x) for x in theta]
+    if len(theta) != theta_size(params):
+        raise ValueError("theta has the wrong length")
+    p = copy.deepcopy(params)
+    for s, m in enumerate(p["modes"]):
+        m["g3"] *= theta[s]
+        m["g4"] *= theta[n + s]
+        m["V1"] *= theta[2 * n + 2]
+        m["V2"] *= theta[2 * n + 3]
+        m["zeta"] *= theta[2 * n + 4]
+        m["gamma"] *= theta[2 * n + 5]
+    for c in p.get("couplings", []):
+        c["g_st"] *= theta[2 * n]
+        c["g_s2t"] *= theta[2 * n + 1]
+        c["g_st2"] *= theta[2 * n + 1]
+    return p
+
+
+def theta_directions(params):
+    """d params / d theta_i for every factor (params are linear in theta): one
+    dictionary per factor with the same layout, every number set to the
+    derivative of that field (zero where theta_i does not enter)."""
+    import copy
+    out = []
+    for i in range(theta_size(params)):
+        e = [0.0] * theta_size(params)
+        e[i] = 1.0
+        p = copy.deepcopy(params)
+        n = len(p["modes"])
+        for s, (m, m0) in enumerate(zip(p["modes"], params["modes"])):
+            for key in ("omega", "g3", "g4", "V1", "V2", "zeta", "gamma", "mu1", "mu2"):
+                m[key] = 0.0
+            m["g3"] = m0["g3"] * e[s]
+            m["g4"] = m0["g4"] * e[n + s]
+            m["V1"] = m0["V1"] * e[2 * n + 2]
+            m["V2"] = m0["V2"] * e[2 * n + 3]
+            m["zeta"] = m0["zeta"] * e[2 * n + 4]
+            m["gamma"] = m0["gamma"] * e[2 * n + 5]
+        for c, c0 in zip(p.get("couplings", []), params.get("couplings", [])):
+            c["g_st"] = c0["g_st"] * e[2 * n]
+            c["g_s2t"] = c0["g_s2t"] * e[2 * n + 1]
+            c["g_st2"] = c0["g_st2"] * e[2 * n + 1]
+            c["mu_st"] = 0.0
+        p["beta"] = 0.0
+        out.append(p)
+    return out
+
+
+def cfg5_small(seed: int = 0):
+    """Reduced gradient workload (same layout as cfg5): two anharmonic modes
+    kept at 3 and 2 levels (d = 6) with bilinear and Fermi couplings, K = 1 Pade
+    term per mode, depth 2 (15 ADOs), dt = 0.1, a 6 x 6 grid every 4 steps and
+    t2 in {0, 8 steps}.  Returns (params, grid, theta_target)."""
+    rng = np.random.default_rng(seed + 77)
+    modes = [_mode(rng, 1.0, n_keep=3, K=1), _mode(rng, 0.45, n_keep=2, K=1)]
+    modes[0]["n_basis"] = 8
+    modes[1]["n_basis"] = 8
+    couplings = [_coupling(0, 1, g_st=float(rng.uniform(0.02, 0.05)),
+                           g_s2t=float(rng.uniform(0.02, 0.05)),
+                           g_st2=float(rng.uniform(0.02, 0.05)), mu_st=0.02)]
+    params = {"modes": modes, "couplings": couplings, "beta": 10.0, "depth": 2,
+              "decomp": "pade", "dt": 0.1}
+    r = rng.choice([-1.0, 1.0], size=theta_size(params))
+    return params, response_grid(6, 4, [0, 8]), [float(1.0 + 0.05 * x) for x in r]
