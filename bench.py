@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 # scaled by the counters' readings for kernels of known size.  Keyed by the
 # kernel source hash: a changed kernel reports traffic null until re-profiled.
 PROFILED_TRAFFIC = {
-    "87c1b457b77a58d3": {"read_GB": 289.2, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
+    "17692ea95720ccad": {"read_GB": 289.2, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
 }
 
 PEAKS = {  # MI355X published dense peaks
@@ -91,7 +91,7 @@ def cpu_baseline(params, budget_s=30.0):
                       f"{len(o.hier)}-ADO model ({dt:.1f} s each); 4 RHS = 1 RK4 step"}
 
 
-def multi_instance(P, torch, precision, stream):
+def multi_instance(P, torch, precision, stream, compare=False):
     """The uneven 64-instance batch (d = 6, 25, 80; 35..5005 ADOs; 64x64 grid at
     t2 = 0): seconds for all 64 responses batched (one launch per size class
     and RK4 stage) and one instance after another, and their agreement."""
@@ -112,19 +112,22 @@ def multi_instance(P, torch, precision, stream):
     Rb = P.heom_batch_response_2d(b, rhos, grid, precision)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    Rs = [P.heom_response_2d(m, r, grid, precision, "adjoint") for m, r in zip(models, rhos)]
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
-    diff = max(float(np.max(np.abs(a - c)) / max(np.max(np.abs(c)), 1e-300)) for a, c in zip(Rb, Rs))
     n1, sps = grid["n1"], grid["steps_per_sample"]
     # single-trajectory RK4 steps: t3 scan (adjoint) + one t1 scan per pathway
     ado_steps = sum(m.n_ado for m in models) * 3 * (n1 - 1) * sps
-    return {"instances": len(models), "grid": [n1, grid["n3"]], "t2": 0, "precision": precision,
-            "d_classes": sorted({m.d for m in models}),
-            "s_batched": t_batch, "s_one_by_one": t_seq, "speedup": t_seq / t_batch,
-            "ado_updates_per_s_batched": ado_steps / t_batch, "max_rel_diff_vs_one_by_one": diff,
-            "rho_eq": "ground state (timing only)"}
+    out = {"instances": len(models), "grid": [n1, grid["n3"]], "t2": 0, "precision": precision,
+           "d_classes": sorted({m.d for m in models}), "s_batched": t_batch,
+           "ado_updates_per_s_batched": ado_steps / t_batch, "rho_eq": "ground state (timing only)"}
+    if compare:
+        t0 = time.perf_counter()
+        Rs = [P.heom_response_2d(m, r, grid, precision, "adjoint") for m, r in zip(models, rhos)]
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t0
+        out["s_one_by_one"] = t_seq
+        out["speedup"] = t_seq / t_batch
+        out["max_rel_diff_vs_one_by_one"] = max(
+            float(np.max(np.abs(a - c)) / max(np.max(np.abs(c)), 1e-300)) for a, c in zip(Rb, Rs))
+    return out
 
 
 def main():
@@ -138,7 +141,8 @@ def main():
     ap.add_argument("--spectrum", type=int, default=1, help="also time one full 2D spectrum")
     ap.add_argument("--eq-steps", type=int, default=200)
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--multi", type=int, default=1, help="also time the 64-instance uneven batch")
+    ap.add_argument("--multi", type=int, default=1,
+                    help="1: also time the 64-instance uneven batch; 2: and one instance at a time")
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "mfma", "mfma_dyn"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -231,7 +235,8 @@ def main():
                                    "equilibration_steps": eq_steps, "finite": bool(np.isfinite(S).all())}
     del s
     if args.multi:
-        line["multi_instance"] = multi_instance(P, torch, args.precision, stream.cuda_stream)
+        line["multi_instance"] = multi_instance(P, torch, args.precision, stream.cuda_stream,
+                                                compare=args.multi > 1)
     if args.cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(params)
     print(json.dumps(line))
