@@ -224,6 +224,59 @@ int heom_response_2d(heom_model* model, const heom_state* rho_eq, const heom_gri
 int heom_spectrum_2d(const double* R_I, const double* R_II, int n1, int n3, double dt_s,
                      double* S_out);
 
+/* ------------------------------------------------------- gradients ----- */
+/* Gradients of a real objective J = Re sum W[q][P][j][k] R[q][P][j][k] of the
+ * third-order responses (weights W from the caller, e.g. heom_spectrum_2d_vjp
+ * of dJ/dS_C) with respect to the operators the HEOM generator and the
+ * dipoles are built from (Sec. II.A operators, Sec. II.B bath terms).  Every
+ * entry is treated as independent (no symmetry imposed).  Caller-owned host
+ * arrays:
+ *   dH  [d*d]                 dJ/dH_S'[a][b]
+ *   dv  [sum_s dims[s]^2]     dJ/dv_s[a][b], mode after mode (V_s = v_s on mode s)
+ *   dmu [d*d]                 dJ/dmu[a][b]; mu+ = mu where N(a) > N(b), mu- = (mu+)^T
+ *   dc  [n_terms*2]           dJ/dRe c_j, dJ/dIm c_j
+ *   dnu [n_terms]             dJ/dnu_j
+ * stationary_steps / stationary_residual are outputs (see heom_response_2d_vjp). */
+typedef struct {
+  double* dH;
+  double* dv;
+  double* dmu;
+  double* dc;
+  double* dnu;
+  int stationary_steps;
+  double stationary_residual;
+} heom_op_grad;
+
+/* Reverse-mode gradient of J through the response computation of
+ * heom_response_2d (adjoint detection method, FP64 propagation): the
+ * detection functional, both pathways' t1 scans, t2 propagations and t3
+ * detection, with the exact discrete adjoint of the RK4 propagator (each
+ * step's derivative is the sum over a + b <= 3 of h^(a+b+1)/(a+b+1)!
+ * <(L^T)^a lambda, dL L^b y>).  Forward states are recomputed from
+ * checkpoints.  rho_is_stationary = 1: rho_eq is the stationary state
+ * (L rho_eq = 0, tr rho_eq,0 = 1) and its dependence on the operators is
+ * included through the adjoint stationary equation, solved by adjoint
+ * propagation until the series term falls below tol x its first term (at most
+ * max_steps; stationary_steps / stationary_residual report it;
+ * HEOM_ERR_NOCONV if not reached); 0: rho_eq is held fixed.  W: host
+ * [n_t2][2][n1][n3] complex.  Needs d <= 80, every mode dimension <= 8 and
+ * K + 1 <= 4 terms per mode (HEOM_ERR_PARAM otherwise). */
+int heom_response_2d_vjp(heom_model* model, const heom_state* rho_eq, const heom_grid* grid, const double* W,
+                         int rho_is_stationary, double tol, int max_steps, heom_op_grad* out);
+
+/* Adjoint of heom_spectrum_2d: weights W[P][j][k] (P = I, II; host,
+ * [2][n1][n3] complex) with sum G . S_C(R_I, R_II) = Re sum W[P] R_P for the
+ * real cotangent G ([2 n3][2 n1], e.g. dJ/dS_C).  Host computation, FP64. */
+int heom_spectrum_2d_vjp(const double* G, int n1, int n3, double dt_s, double* W_out);
+
+/* Chain from operator gradients to parameters: out[i] = sum over all
+ * operator entries of g x d(operators)/d(params) along dirs[i], the
+ * derivative of the host model build taken by central differences with the
+ * given step (dirs[i] has the layout of params and holds the derivative of
+ * every number; integer fields are ignored).  Host computation. */
+int heom_params_vjp(const heom_params* params, const heom_params* dirs, int n_dirs, double step,
+                    const heom_op_grad* g, double* out);
+
 /* ------------------------------------------- several model instances -- */
 /* A batch of models (instances) of possibly different sizes, propagated
  * together: every RK4 stage is one persistent matrix-core launch per size

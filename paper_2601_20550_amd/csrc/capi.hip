@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <map>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -17,6 +18,7 @@
 
 #include "heom2dvs.h"
 #include "kernels.h"
+#include "grad.h"
 #include "model.h"
 
 namespace {
@@ -133,6 +135,8 @@ struct heom_model {
   DevBuf Hp64, Hp32;  // H zero-padded to a multiple of 16 (matrix-core kernel)
   int kernel[2] = {HEOM_KERNEL_MFMA, HEOM_KERNEL_MFMA};  // per precision
   DevBuf nb_ptr[2], nb_idx[2], nb_a64[2], nb_a32[2];
+  DevBuf nb_tj, ado_n;  // forward-table (term, count) pairs and ADO indices (gradient kernels)
+  heom::GradOps gops{};
   heom::DevOps<double> ops64[2];
   heom::DevOps<float> ops32[2];
   // scratch: two hierarchy-sized work buffers per precision, grown on demand
@@ -244,6 +248,26 @@ void upload_model(heom_model* m) {
     m->Hp32 = f32(hp);
     if (!heom::mfma_supported<double>(d)) m->kernel[HEOM_FP64] = HEOM_KERNEL_GENERIC;
     if (!heom::mfma_supported<float>(d)) m->kernel[HEOM_FP32] = HEOM_KERNEL_GENERIC;
+  }
+  {
+    m->nb_tj = upload_vec(hm.fwd.tj, st);
+    m->ado_n = upload_vec(hm.ado_n, st);
+    heom::GradOps& g = m->gops;
+    g.v = m->v64.as<double>();
+    g.nb_ptr = m->nb_ptr[0].as<int>();
+    g.nb_idx = m->nb_idx[0].as<int>();
+    g.nb_a = m->nb_a64[0].as<double>();
+    g.nb_tj = m->nb_tj.as<int>();
+    g.ado_n = m->ado_n.as<int>();
+    for (int s = 0; s < 4; ++s) {
+      g.v_off[s] = v_off[s];
+      g.dims[s] = hm.dims[s];
+      g.strides[s] = hm.strides[s];
+    }
+    g.n_modes = hm.n_modes;
+    g.d = hm.d;
+    g.n_ado = hm.n_ado;
+    g.n_terms = hm.n_terms;
   }
   m->red_result = DevBuf(sizeof(double) * 4);
   m->has_device = true;
@@ -702,6 +726,387 @@ void batch_response_adjoint(heom_batch* b, const heom_state* const* rho_eq, cons
 
 }  // namespace
 
+namespace {
+
+// ----------------------------------------------------------------------------
+// Reverse-mode gradient of J = Re sum W R (heom_response_2d_vjp).  FP64.
+//
+// The RK4 propagator is Phi = p(hL), p(z) = 1 + z + z^2/2 + z^3/6 + z^4/24, and
+// for a step y -> Phi y with adjoint lambda (the cotangent of Phi y) the
+// operator derivative is <lambda, dPhi y> = sum_{a+b<=3} c_{a+b}
+// <(L^T)^a lambda, dL L^b y>, c_m = h^(m+1)/(m+1)!.  <u, dL z> is contracted
+// into operator gradients by the grad.hip kernels (K below).
+
+struct GradCtx {
+  heom_model* m;
+  long long te;    // doubles per trajectory
+  double h;
+  DevBuf partH, partP, partM;   // [max_parts][d*d]
+  DevBuf gv, gc, gnu;           // device accumulators
+  DevBuf C4, C1;                // combine coefficients (4x4 powers -> z'_a; 1x4 step)
+  // sweep buffers
+  DevBuf S, Ob, Zp;
+  long long cap_S = 0, cap_O = 0;
+};
+
+DevBuf upload_coef(const std::vector<double>& c, hipStream_t st) { return upload_vec(c, st); }
+
+void zero_dev(DevBuf& b, hipStream_t st) {
+  if (b.bytes) hip_check(hipMemsetAsync(b.p, 0, b.bytes, st), "memset");
+}
+
+void grad_init(GradCtx& g, heom_model* m) {
+  g.m = m;
+  g.te = m->traj_elems();
+  g.h = m->hm.dt;
+  const size_t dd = static_cast<size_t>(m->hm.d) * m->hm.d;
+  const size_t parts = static_cast<size_t>(heom::grad_max_parts()) * dd * sizeof(double);
+  g.partH = DevBuf(parts);
+  g.partP = DevBuf(parts);
+  g.partM = DevBuf(parts);
+  size_t nv = 0;
+  for (int s = 0; s < m->hm.n_modes; ++s) nv += static_cast<size_t>(m->hm.dims[s]) * m->hm.dims[s];
+  g.gv = DevBuf(nv * sizeof(double));
+  g.gc = DevBuf(static_cast<size_t>(m->hm.n_terms) * 2 * sizeof(double));
+  g.gnu = DevBuf(static_cast<size_t>(m->hm.n_terms) * sizeof(double));
+  for (DevBuf* b : {&g.partH, &g.partP, &g.partM, &g.gv, &g.gc, &g.gnu}) zero_dev(*b, m->stream);
+  const double h = g.h;
+  const double c[4] = {h, h * h / 2.0, h * h * h / 6.0, h * h * h * h / 24.0};
+  std::vector<double> c4(32, 0.0);  // z'_a = sum_b c_{a+b} w_b
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; a + b < 4; ++b) c4[2 * (a * 4 + b)] = c[a + b];
+  g.C4 = upload_coef(c4, m->stream);
+  std::vector<double> c1 = {1.0, 0.0, h, 0.0, h * h / 2.0, 0.0, h * h * h / 6.0, 0.0};
+  g.C1 = upload_coef(c1, m->stream);
+}
+
+// <u, dL z> over n_traj trajectories
+void k_generator(GradCtx& g, const double* u, const double* z, int n_traj) {
+  heom_model* m = g.m;
+  const long long items = static_cast<long long>(n_traj) * m->hm.n_ado;
+  heom::launch_gemm_grad(u, z, items, m->hm.d, 0.0, -1.0, g.partH.as<double>(), m->stream);
+  int off = 0;
+  for (int s = 0; s < m->hm.n_modes; ++s) {
+    heom::launch_nb_grad(m->gops, s, u, z, items, g.gv.as<double>() + off, g.gc.as<double>(), g.gnu.as<double>(),
+                         m->stream);
+    off += m->hm.dims[s] * m->hm.dims[s];
+  }
+}
+
+// <u, dD^x z> into the mu+ or mu- accumulator
+void k_dipole(GradCtx& g, int op, const double* u, const double* z, int n_traj) {
+  heom_model* m = g.m;
+  const long long items = static_cast<long long>(n_traj) * m->hm.n_ado;
+  double* part = op == HEOM_OP_MU_PLUS ? g.partP.as<double>() : g.partM.as<double>();
+  heom::launch_gemm_grad(u, z, items, m->hm.d, 1.0, 0.0, part, m->stream);
+}
+
+void combine(GradCtx& g, const double* in, long long in_stride, int n_in, double* out, long long out_stride,
+             int n_out, const double* coef, int acc, int n_traj) {
+  heom::launch_combine(in, in_stride, n_in, out, out_stride, n_out, coef, acc,
+                       static_cast<long long>(n_traj) * g.m->hm.n_ado, g.m->hm.d, g.m->stream);
+}
+
+void ensure(DevBuf& b, long long& cap, long long doubles, hipStream_t st) {
+  if (cap < doubles) {
+    hip_check(hipStreamSynchronize(st), "sync");
+    b = DevBuf();
+    b = DevBuf(static_cast<size_t>(doubles) * sizeof(double));
+    cap = doubles;
+  }
+}
+
+// Adjoint sweep over one segment of n steps.  The stored side starts at S0
+// (nt trajectories) and is propagated forward with the generator of its own
+// kind (L, or L^T if stored_adjoint); the other side O holds its state at the
+// segment end and is carried back to the segment start with the transposed
+// generator.  Accumulates the operator derivatives of every step.
+void sweep(GradCtx& g, const double* S0, double* O, int nt, int n, bool stored_adjoint) {
+  if (n <= 0) return;
+  heom_model* m = g.m;
+  hipStream_t st = m->stream;
+  const long long N = static_cast<long long>(nt) * g.te;
+  ensure(g.S, g.cap_S, static_cast<long long>(n) * 4 * N, st);
+  long long capO = std::max(g.cap_O, 0LL);
+  ensure(g.Ob, g.cap_O, 8 * N, st);
+  (void)capO;
+  double* S = g.S.as<double>();
+  double* Ob = g.Ob.as<double>();       // Ob[0..3]: on-the-fly powers
+  double* Zp = Ob + 4 * N;              // combined partners z'_a
+  const bool gs = stored_adjoint, go = !stored_adjoint;
+  const double h = g.h;
+  // forward recompute with powers
+  hip_check(hipMemcpyAsync(S, S0, N * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+  for (int k = 0; k < n; ++k) {
+    double* Sk = S + static_cast<long long>(k) * 4 * N;
+    for (int p = 1; p < 4; ++p) stage<double>(m, gs, Sk + (p - 1) * N, nullptr, Sk + p * N, 1.0, nt);
+    if (k + 1 < n) {
+      double* nx = S + static_cast<long long>(k + 1) * 4 * N;
+      combine(g, Sk, N, 4, nx, N, 1, g.C1.as<double>(), 0, nt);
+      stage<double>(m, gs, Sk + 3 * N, nx, nx, h * h * h * h / 24.0, nt);
+    }
+  }
+  // backward
+  hip_check(hipMemcpyAsync(Ob, O, N * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+  for (int k = n - 1; k >= 0; --k) {
+    double* Sk = S + static_cast<long long>(k) * 4 * N;
+    for (int p = 1; p < 4; ++p) stage<double>(m, go, Ob + (p - 1) * N, nullptr, Ob + p * N, 1.0, nt);
+    if (!stored_adjoint) {
+      // stored = forward y (L powers w_b), on the fly = lambda (L^T powers u_a)
+      combine(g, Sk, N, 4, Zp, N, 4, g.C4.as<double>(), 0, nt);
+      for (int a = 0; a < 4; ++a) k_generator(g, Ob + a * N, Zp + a * N, nt);
+    } else {
+      // stored = L^T powers u_a, on the fly = L powers w_b
+      combine(g, Ob, N, 4, Zp, N, 4, g.C4.as<double>(), 0, nt);
+      for (int a = 0; a < 4; ++a) k_generator(g, Sk + a * N, Zp + a * N, nt);
+    }
+    // O(k) = Phi_O O(k+1)
+    combine(g, Ob, N, 4, Ob, N, 1, g.C1.as<double>(), 0, nt);
+    stage<double>(m, go, Ob + 3 * N, Ob, Ob, h * h * h * h / 24.0, nt);
+  }
+  hip_check(hipMemcpyAsync(O, Ob, N * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+}
+
+void copy_dev(double* dst, const double* src, long long n, hipStream_t st) {
+  hip_check(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+}
+
+void response_vjp(heom_model* m, const heom_state* rho_eq, const heom_grid& gr, const double* W, bool stationary,
+                  double tol, int max_steps, heom_op_grad* out) {
+  GradCtx g;
+  grad_init(g, m);
+  hipStream_t st = m->stream;
+  const int d = m->hm.d, n_ado = m->hm.n_ado;
+  const int n1 = gr.n1, n3 = gr.n3, sps = gr.steps_per_sample, nq = gr.n_t2;
+  const long long te = g.te;
+  const double* rho = rho_eq->buf.as<double>();
+  auto Wc = [&](int q, int P, int j, int k, int part) {
+    return W[2 * (((static_cast<long long>(q) * 2 + P) * n1 + j) * n3 + k) + part];
+  };
+  // 1. detection functional l(k sps) and Psi_k = (mu+^x)^T l(k sps)
+  DevBuf Lk(static_cast<size_t>(n3) * te * sizeof(double)), Psi(static_cast<size_t>(n3) * te * sizeof(double));
+  {
+    std::vector<double> h(static_cast<size_t>(te), 0.0);
+    for (int a = 0; a < d; ++a)
+      for (int c = 0; c < d; ++c) h[static_cast<size_t>(a) * d + c] = m->hm.mu[static_cast<size_t>(c) * d + a];
+    hip_check(hipMemcpyAsync(Lk.p, h.data(), te * sizeof(double), hipMemcpyHostToDevice, st), "upload");
+    hip_check(hipStreamSynchronize(st), "sync");
+    for (int k = 1; k < n3; ++k) {
+      copy_dev(Lk.as<double>() + k * te, Lk.as<double>() + (k - 1) * te, te, st);
+      rk4_steps_scratch<double>(m, Lk.as<double>() + k * te, 1, sps, true);
+    }
+    heom::launch_commutator<double>(m->mu64[HEOM_OP_MU_PLUS].as<double>(), 1, Lk.as<double>(), Psi.as<double>(), d,
+                                    static_cast<long long>(n3) * n_ado, st);
+  }
+  DevBuf phi(static_cast<size_t>(n3) * te * sizeof(double));
+  zero_dev(phi, st);
+  DevBuf grho(static_cast<size_t>(te) * sizeof(double));
+  zero_dev(grho, st);
+  DevBuf Xc(static_cast<size_t>(n1) * te * sizeof(double)), bsrc(static_cast<size_t>(n1) * te * sizeof(double));
+  DevBuf tmp1(static_cast<size_t>(te) * sizeof(double));
+  const int T_max = gr.t2_steps[nq - 1];
+  const int CSEG = 16;
+  // boundaries of the t2 sweep: every t2 sample and every CSEG steps
+  std::vector<int> bnd = {0};
+  for (int t = CSEG; t < T_max; t += CSEG) bnd.push_back(t);
+  for (int q = 0; q < nq; ++q) bnd.push_back(gr.t2_steps[q]);
+  std::sort(bnd.begin(), bnd.end());
+  bnd.erase(std::unique(bnd.begin(), bnd.end()), bnd.end());
+  const int nbd = static_cast<int>(bnd.size());
+  // trajectories per chunk from free memory: chunk state, checkpoints, sweep buffers, rk4 scratch
+  const long long per_traj = (nbd + 1 + 4 * CSEG + 8 + 2 + 1) * te * static_cast<long long>(sizeof(double));
+  const size_t fr = free_device_bytes();
+  const size_t budget = fr > (size_t(2) << 30) ? fr - (size_t(2) << 30) : 0;
+  const int nc = static_cast<int>(std::max<long long>(1, std::min<long long>(n1, budget / per_traj)));
+  const int pw_d[2][2] = {{HEOM_OP_MU_MINUS, HEOM_OP_MU_PLUS}, {HEOM_OP_MU_PLUS, HEOM_OP_MU_MINUS}};
+  for (int P = 0; P < 2; ++P) {
+    const int D1 = pw_d[P][0], D2 = pw_d[P][1];
+    // t1 scan with checkpoints at every sample
+    heom::launch_commutator<double>(m->mu64[D1].as<double>(), 0, rho, Xc.as<double>(), d, n_ado, st);
+    for (int j = 1; j < n1; ++j) {
+      copy_dev(Xc.as<double>() + j * te, Xc.as<double>() + (j - 1) * te, te, st);
+      rk4_steps_scratch<double>(m, Xc.as<double>() + j * te, 1, sps, false);
+    }
+    DevBuf Y(static_cast<size_t>(nc) * te * sizeof(double)), A(static_cast<size_t>(nc) * te * sizeof(double));
+    DevBuf CK(static_cast<size_t>(std::max(nbd - 1, 1)) * nc * te * sizeof(double));
+    for (int j0 = 0; j0 < n1; j0 += nc) {
+      const int c = std::min(nc, n1 - j0);
+      const long long N = static_cast<long long>(c) * te;
+      heom::launch_commutator<double>(m->mu64[D2].as<double>(), 0, Xc.as<double>() + j0 * te, Y.as<double>(), d,
+                                      static_cast<long long>(c) * n_ado, st);
+      // forward over t2 with checkpoints; detection cotangent phi_k += sum_j (-i W) Y_j(T_q)
+      for (int i = 0; i < nbd; ++i) {
+        if (i + 1 < nbd) copy_dev(CK.as<double>() + i * N, Y.as<double>(), N, st);
+        for (int q = 0; q < nq; ++q) {
+          if (gr.t2_steps[q] != bnd[i]) continue;
+          std::vector<double> cf(static_cast<size_t>(n3) * c * 2);
+          for (int k = 0; k < n3; ++k)
+            for (int jj = 0; jj < c; ++jj) {  // -i W
+              cf[2 * (k * c + jj)] = Wc(q, P, j0 + jj, k, 1);
+              cf[2 * (k * c + jj) + 1] = -Wc(q, P, j0 + jj, k, 0);
+            }
+          DevBuf cfd = upload_coef(cf, st);
+          combine(g, Y.as<double>(), te, c, phi.as<double>(), te, n3, cfd.as<double>(), 1, 1);
+          hip_check(hipStreamSynchronize(st), "sync");
+        }
+        if (i + 1 < nbd) rk4_steps_scratch<double>(m, Y.as<double>(), c, bnd[i + 1] - bnd[i], false);
+      }
+      // backward over t2: sources sigma_q = sum_k (-i W) Psi_k at t2_q
+      zero_dev(A, st);
+      for (int i = nbd - 1; i >= 0; --i) {
+        for (int q = 0; q < nq; ++q) {
+          if (gr.t2_steps[q] != bnd[i]) continue;
+          std::vector<double> cf(static_cast<size_t>(c) * n3 * 2);
+          for (int jj = 0; jj < c; ++jj)
+            for (int k = 0; k < n3; ++k) {
+              cf[2 * (jj * n3 + k)] = Wc(q, P, j0 + jj, k, 1);
+              cf[2 * (jj * n3 + k) + 1] = -Wc(q, P, j0 + jj, k, 0);
+            }
+          DevBuf cfd = upload_coef(cf, st);
+          combine(g, Psi.as<double>(), te, n3, A.as<double>(), te, c, cfd.as<double>(), 1, 1);
+          hip_check(hipStreamSynchronize(st), "sync");
+        }
+        if (i > 0) sweep(g, CK.as<double>() + (i - 1) * N, A.as<double>(), c, bnd[i] - bnd[i - 1], false);
+      }
+      // A = cotangent of the snapshots D2^x X(t1_j)
+      k_dipole(g, D2, A.as<double>(), Xc.as<double>() + j0 * te, c);
+      heom::launch_commutator<double>(m->mu64[D2].as<double>(), 1, A.as<double>(), bsrc.as<double>() + j0 * te, d,
+                                      static_cast<long long>(c) * n_ado, st);
+    }
+    // t1 backward
+    DevBuf b(static_cast<size_t>(te) * sizeof(double));
+    copy_dev(b.as<double>(), bsrc.as<double>() + (n1 - 1) * te, te, st);
+    std::vector<double> one = {1.0, 0.0};
+    DevBuf oned = upload_coef(one, st);
+    for (int j = n1 - 1; j >= 1; --j) {
+      sweep(g, Xc.as<double>() + (j - 1) * te, b.as<double>(), 1, sps, false);
+      combine(g, bsrc.as<double>() + (j - 1) * te, te, 1, b.as<double>(), te, 1, oned.as<double>(), 1, 1);
+    }
+    k_dipole(g, D1, b.as<double>(), rho, 1);
+    heom::launch_commutator<double>(m->mu64[D1].as<double>(), 1, b.as<double>(), tmp1.as<double>(), d, n_ado, st);
+    combine(g, tmp1.as<double>(), te, 1, grho.as<double>(), te, 1, oned.as<double>(), 1, 1);
+    hip_check(hipStreamSynchronize(st), "sync");
+  }
+  // detection side: Psi_k = (mu+^x)^T l(k sps)
+  {
+    DevBuf csrc(static_cast<size_t>(n3) * te * sizeof(double));
+    heom::launch_commutator<double>(m->mu64[HEOM_OP_MU_PLUS].as<double>(), 0, phi.as<double>(), csrc.as<double>(),
+                                    d, static_cast<long long>(n3) * n_ado, st);
+    k_dipole(g, HEOM_OP_MU_PLUS, Lk.as<double>(), phi.as<double>(), n3);
+    DevBuf cc(static_cast<size_t>(te) * sizeof(double));
+    copy_dev(cc.as<double>(), csrc.as<double>() + (n3 - 1) * te, te, st);
+    std::vector<double> one = {1.0, 0.0};
+    DevBuf oned = upload_coef(one, st);
+    for (int k = n3 - 1; k >= 1; --k) {
+      sweep(g, Lk.as<double>() + (k - 1) * te, cc.as<double>(), 1, sps, true);
+      combine(g, csrc.as<double>() + (k - 1) * te, te, 1, cc.as<double>(), te, 1, oned.as<double>(), 1, 1);
+    }
+    // l_0 = mu^T on ADO 0: dJ/dmu[a][b] += Re c(0)[0][b][a]
+    std::vector<double> c0(static_cast<size_t>(d) * d);
+    hip_check(hipMemcpyAsync(c0.data(), cc.p, c0.size() * sizeof(double), hipMemcpyDeviceToHost, st), "copy");
+    hip_check(hipStreamSynchronize(st), "sync");
+    for (int a = 0; a < d; ++a)
+      for (int bb = 0; bb < d; ++bb) out->dmu[a * d + bb] = c0[static_cast<size_t>(bb) * d + a];
+  }
+  // stationary state: <g_rho, d rho_eq> = <P(hL^T) kd, dL rho_eq>, kd = h sum_n (Phi^T)^n r
+  out->stationary_steps = 0;
+  out->stationary_residual = 0.0;
+  if (stationary) {
+    DevBuf work(heom::pair_work_doubles(1, 1, n_ado, d) * sizeof(double));
+    DevBuf sdev(2 * sizeof(double));
+    heom::launch_pairing<double>(grho.as<double>(), 1, rho, 1, n_ado, d, 1.0, 0.0, work.as<double>(),
+                                 sdev.as<double>(), st);
+    double sgr[2];
+    hip_check(hipMemcpyAsync(sgr, sdev.p, sizeof(sgr), hipMemcpyDeviceToHost, st), "copy");
+    std::vector<double> blk(static_cast<size_t>(2) * d * d);
+    hip_check(hipMemcpyAsync(blk.data(), grho.p, blk.size() * sizeof(double), hipMemcpyDeviceToHost, st), "copy");
+    hip_check(hipStreamSynchronize(st), "sync");
+    for (int a = 0; a < d; ++a) {
+      blk[static_cast<size_t>(a) * d + a] -= sgr[0];
+      blk[static_cast<size_t>(d) * d + static_cast<size_t>(a) * d + a] -= sgr[1];
+    }
+    hip_check(hipMemcpyAsync(grho.p, blk.data(), blk.size() * sizeof(double), hipMemcpyHostToDevice, st), "copy");
+    hip_check(hipStreamSynchronize(st), "sync");
+    const double r0 = absmax<double>(m, grho.as<double>(), n_ado);
+    DevBuf kd(static_cast<size_t>(te) * sizeof(double));
+    std::vector<double> hc = {g.h, 0.0};
+    DevBuf hcd = upload_coef(hc, st);
+    combine(g, grho.as<double>(), te, 1, kd.as<double>(), te, 1, hcd.as<double>(), 0, 1);
+    double res = r0;
+    int n = 0;
+    const int check_every = 50;
+    while (true) {
+      if (r0 == 0.0 || res <= tol * r0) break;
+      if (n >= max_steps) break;
+      const int k = std::min(check_every, max_steps - n);
+      for (int i = 0; i < k; ++i) {
+        rk4_steps_scratch<double>(m, grho.as<double>(), 1, 1, true);
+        combine(g, grho.as<double>(), te, 1, kd.as<double>(), te, 1, hcd.as<double>(), 1, 1);
+      }
+      n += k;
+      res = absmax<double>(m, grho.as<double>(), n_ado);
+    }
+    out->stationary_steps = n;
+    out->stationary_residual = r0 > 0 ? res / r0 : 0.0;
+    if (!(res <= tol * r0) && r0 != 0.0)
+      throw HeomError(HEOM_ERR_NOCONV, "adjoint stationary series did not converge within max_steps");
+    DevBuf t1(static_cast<size_t>(te) * sizeof(double)), t2(static_cast<size_t>(te) * sizeof(double));
+    stage<double>(m, true, kd.as<double>(), kd.as<double>(), t1.as<double>(), g.h / 4.0, 1);
+    stage<double>(m, true, t1.as<double>(), kd.as<double>(), t2.as<double>(), g.h / 3.0, 1);
+    stage<double>(m, true, t2.as<double>(), kd.as<double>(), t1.as<double>(), g.h / 2.0, 1);
+    k_generator(g, t1.as<double>(), rho, 1);
+    hip_check(hipStreamSynchronize(st), "sync");
+  }
+  // reductions and the dipole chain mu -> (mu, mu+, mu-)
+  const long long dd = static_cast<long long>(d) * d;
+  DevBuf red(3 * dd * sizeof(double));
+  zero_dev(red, st);
+  heom::launch_reduce_parts(g.partH.as<double>(), heom::grad_max_parts(), dd, red.as<double>(), st);
+  heom::launch_reduce_parts(g.partP.as<double>(), heom::grad_max_parts(), dd, red.as<double>() + dd, st);
+  heom::launch_reduce_parts(g.partM.as<double>(), heom::grad_max_parts(), dd, red.as<double>() + 2 * dd, st);
+  std::vector<double> hr(3 * dd);
+  hip_check(hipMemcpyAsync(hr.data(), red.p, hr.size() * sizeof(double), hipMemcpyDeviceToHost, st), "copy");
+  size_t nv = g.gv.bytes / sizeof(double);
+  hip_check(hipMemcpyAsync(out->dv, g.gv.p, nv * sizeof(double), hipMemcpyDeviceToHost, st), "copy");
+  hip_check(hipMemcpyAsync(out->dc, g.gc.p, g.gc.bytes, hipMemcpyDeviceToHost, st), "copy");
+  hip_check(hipMemcpyAsync(out->dnu, g.gnu.p, g.gnu.bytes, hipMemcpyDeviceToHost, st), "copy");
+  hip_check(hipStreamSynchronize(st), "sync");
+  const auto& Nq = m->hm.quanta;
+  for (long long i = 0; i < dd; ++i) out->dH[i] = hr[i];
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) {
+      if (Nq[a] > Nq[b]) out->dmu[a * d + b] += hr[dd + a * d + b] + hr[2 * dd + static_cast<long long>(b) * d + a];
+    }
+  auto finite = [](const double* x, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+      if (!std::isfinite(x[i])) return false;
+    return true;
+  };
+  if (!finite(out->dH, dd) || !finite(out->dmu, dd) || !finite(out->dv, nv) ||
+      !finite(out->dc, 2 * m->hm.n_terms) || !finite(out->dnu, m->hm.n_terms))
+    throw HeomError(HEOM_ERR_UNSTABLE, "non-finite gradient");
+}
+
+// host model operators flattened in the heom_op_grad layout
+struct OpVec {
+  std::vector<double> H, v, mu, c, nu;
+};
+
+OpVec op_vec(const heom::HostModel& hm) {
+  OpVec o;
+  o.H = hm.H;
+  for (int s = 0; s < hm.n_modes; ++s) o.v.insert(o.v.end(), hm.v[s].begin(), hm.v[s].end());
+  o.mu = hm.mu;
+  for (int j = 0; j < hm.n_terms; ++j) {
+    o.c.push_back(hm.c[j].real());
+    o.c.push_back(hm.c[j].imag());
+  }
+  o.nu = hm.nu;
+  return o;
+}
+
+}  // namespace
+
 // ============================================================== C ABI =====
 
 extern "C" {
@@ -1124,6 +1529,124 @@ int heom_spectrum_2d(const double* R_I, const double* R_II, int n1, int n3, doub
     heom::launch_spectrum(dI.as<double>(), dII.as<double>(), n1, n3, dt_s, work.as<double>(), S.as<double>(),
                           nullptr);
     hip_check(hipMemcpy(S_out, S.p, S.bytes, hipMemcpyDeviceToHost), "download");
+  });
+}
+
+int heom_response_2d_vjp(heom_model* m, const heom_state* rho_eq, const heom_grid* grid, const double* W,
+                         int rho_is_stationary, double tol, int max_steps, heom_op_grad* out) {
+  return guarded([&] {
+    require_device(m);
+    require_state(m, rho_eq);
+    if (!grid || !W || !out || !out->dH || !out->dv || !out->dmu || !out->dc || !out->dnu)
+      throw HeomError(HEOM_ERR_PARAM, "null argument");
+    if (rho_eq->precision != HEOM_FP64 || rho_eq->n_traj != 1)
+      throw HeomError(HEOM_ERR_STATE, "rho_eq must be an FP64 state with one trajectory");
+    const heom_grid& g = *grid;
+    if (g.n1 < 1 || g.n3 < 1 || g.steps_per_sample < 1 || g.n_t2 < 1 || !g.t2_steps)
+      throw HeomError(HEOM_ERR_PARAM, "bad grid");
+    for (int i = 0; i < g.n_t2; ++i)
+      if (g.t2_steps[i] < 0 || (i && g.t2_steps[i] < g.t2_steps[i - 1]))
+        throw HeomError(HEOM_ERR_PARAM, "t2_steps must be non-negative and non-decreasing");
+    if (max_steps < 0 || !(tol >= 0.0)) throw HeomError(HEOM_ERR_PARAM, "bad tol / max_steps");
+    int kmax = 0;
+    for (int s = 0; s < m->hm.n_modes; ++s) {
+      int k = 0;
+      for (int j = 0; j < m->hm.n_terms; ++j) k += m->hm.term_mode[j] == s;
+      kmax = std::max(kmax, k);
+    }
+    if (!heom::grad_supported(m->hm.d, m->hm.dims, m->hm.n_modes, kmax))
+      throw HeomError(HEOM_ERR_PARAM, "gradient needs d <= 80, mode dimensions <= 8 and <= 4 terms per mode");
+    response_vjp(m, rho_eq, g, W, rho_is_stationary != 0, tol, max_steps, out);
+  });
+}
+
+int heom_spectrum_2d_vjp(const double* G, int n1, int n3, double dt_s, double* W_out) {
+  return guarded([&] {
+    if (!G || !W_out || n1 < 1 || n3 < 1 || !(dt_s > 0)) throw HeomError(HEOM_ERR_PARAM, "bad arguments");
+    // S_P = Im(dt^2 E3 R^T E1^T), E(W,t) = w_t exp(iWt); S_C = -(S_I(W3,-W1) + S_II(W3,W1));
+    // Im z = Re(-i z)  =>  W_P[j][k] = i dt^2 sum G[m3][m1] E3[m3][k] E1_P[m1][j]
+    const double two_pi = 6.283185307179586476925287;
+    auto wgt = [](int k) { return k == 0 ? 0.5 : 1.0; };
+    for (int P = 0; P < 2; ++P) {
+      const double sgn1 = P == 0 ? -1.0 : 1.0;
+      // T[m3][j] = sum_m1 G[m3][m1] E1_P[m1][j]
+      std::vector<std::complex<double>> T(static_cast<size_t>(2 * n3) * n1);
+      for (int m3 = 0; m3 < 2 * n3; ++m3)
+        for (int j = 0; j < n1; ++j) {
+          std::complex<double> acc = 0.0;
+          for (int m1 = 0; m1 < 2 * n1; ++m1) {
+            const double w1 = sgn1 * two_pi * (m1 - n1) / (2.0 * n1 * dt_s);
+            const double ph = w1 * dt_s * j;
+            acc += G[static_cast<size_t>(m3) * 2 * n1 + m1] * std::complex<double>(std::cos(ph), std::sin(ph));
+          }
+          T[static_cast<size_t>(m3) * n1 + j] = acc * wgt(j);
+        }
+      for (int j = 0; j < n1; ++j)
+        for (int k = 0; k < n3; ++k) {
+          std::complex<double> acc = 0.0;
+          for (int m3 = 0; m3 < 2 * n3; ++m3) {
+            const double w3 = two_pi * (m3 - n3) / (2.0 * n3 * dt_s);
+            const double ph = w3 * dt_s * k;
+            acc += T[static_cast<size_t>(m3) * n1 + j] * std::complex<double>(std::cos(ph), std::sin(ph));
+          }
+          const std::complex<double> w = std::complex<double>(0.0, 1.0) * dt_s * dt_s * wgt(k) * acc;
+          const size_t o = 2 * ((static_cast<size_t>(P) * n1 + j) * n3 + k);
+          W_out[o] = w.real();
+          W_out[o + 1] = w.imag();
+        }
+    }
+  });
+}
+
+int heom_params_vjp(const heom_params* params, const heom_params* dirs, int n_dirs, double step,
+                    const heom_op_grad* g, double* out) {
+  return guarded([&] {
+    if (!params || !dirs || n_dirs < 0 || !g || !out || !(step > 0))
+      throw HeomError(HEOM_ERR_PARAM, "bad arguments");
+    const heom_params base = copy_check(params);
+    for (int i = 0; i < n_dirs; ++i) {
+      const heom_params& dp = dirs[i];
+      if (dp.n_modes != base.n_modes || dp.n_couplings != base.n_couplings)
+        throw HeomError(HEOM_ERR_PARAM, "direction layout differs from params");
+      auto shifted = [&](double e) {
+        std::vector<heom_mode> modes(base.modes, base.modes + base.n_modes);
+        std::vector<heom_coupling> cps(base.couplings, base.couplings + base.n_couplings);
+        for (int s = 0; s < base.n_modes; ++s) {
+          const heom_mode& dm = dp.modes[s];
+          heom_mode& mm = modes[s];
+          mm.omega += e * dm.omega;
+          mm.g3 += e * dm.g3;
+          mm.g4 += e * dm.g4;
+          mm.V1 += e * dm.V1;
+          mm.V2 += e * dm.V2;
+          mm.zeta += e * dm.zeta;
+          mm.gamma += e * dm.gamma;
+          mm.mu1 += e * dm.mu1;
+          mm.mu2 += e * dm.mu2;
+        }
+        for (int c = 0; c < base.n_couplings; ++c) {
+          const heom_coupling& dc = dp.couplings[c];
+          cps[c].g_st += e * dc.g_st;
+          cps[c].g_s2t += e * dc.g_s2t;
+          cps[c].g_st2 += e * dc.g_st2;
+          cps[c].mu_st += e * dc.mu_st;
+        }
+        heom_params p = base;
+        p.modes = modes.data();
+        p.couplings = cps.data();
+        p.beta = base.beta + e * dp.beta;
+        return op_vec(heom::build_host_model(p));
+      };
+      const OpVec a = shifted(step), b = shifted(-step);
+      auto dot = [&](const std::vector<double>& x, const std::vector<double>& y, const double* gg) {
+        double t = 0.0;
+        for (size_t k = 0; k < x.size(); ++k) t += gg[k] * (x[k] - y[k]);
+        return t;
+      };
+      out[i] = (dot(a.H, b.H, g->dH) + dot(a.v, b.v, g->dv) + dot(a.mu, b.mu, g->dmu) + dot(a.c, b.c, g->dc) +
+                dot(a.nu, b.nu, g->dnu)) /
+               (2.0 * step);
+    }
   });
 }
 

@@ -1,0 +1,520 @@
+// Kernels of the adjoint (reverse-mode) gradient of the responses, FP64.
+//
+// The HEOM generator L (Sec. II.B, Eq. HEOM_DB) is linear in the system
+// Hamiltonian H, in the single-mode coupling operators v_s (entering as
+// V_s = v_s on mode s), in the bath coefficients c_j and in the rates nu_j.
+// For an adjoint hierarchy u and a forward hierarchy z, the derivative of the
+// bilinear pairing <u, L z> (sum over all ADOs and matrix elements, no
+// conjugation) with respect to those operators is a sum over ADOs n of
+//
+//   dH   : Re(-i (u_n z_n^T - z_n^T u_n))
+//   dv_s : Im(TL) - Im(TR),  TL[a][a'] = sum_{r,y} u_n[(a,r)][y] zL_s[(a',r)][y],
+//                            TR[a][a'] = sum_{x,r} zR_s[x][(a,r)] u_n[x][(a',r)],
+//          zL_s = sum_{up j in s} z_{n+e_j} + sum_{down j in s} n_j c_j z_{n-e_j},
+//          zR_s = the same with conj(c_j),   ((a,r): mode-s digit a, other digits r)
+//   dRe c_j : n_j Im(<V_s u_n, z_{n-e_j}> - <u_n V_s, z_{n-e_j}>)
+//   dIm c_j : n_j Re(<V_s u_n, z_{n-e_j}> + <u_n V_s, z_{n-e_j}>)
+//   dnu_j   : -n_j Re <u_n, z_n>
+//
+// The same pairing with a dipole commutator D^x in place of L gives
+// dD = Re(u z^T - z^T u) (factor f = 1 in gemm_grad instead of -i).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <stdexcept>
+#include <string>
+
+#include "grad.h"
+
+namespace heom {
+
+namespace {
+
+constexpr int GT = 256;           // threads per workgroup
+constexpr int MAXDS = 8;          // largest single-mode dimension supported
+constexpr int MAXQ = 8;           // neighbour entries per (ADO, mode)
+constexpr int MAXDOWN = 4;        // lower neighbours per (ADO, mode)
+
+void check(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int g_cus = 0;
+int cus() {
+  if (!g_cus) {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+      g_cus = p.multiProcessorCount;
+    if (g_cus <= 0) g_cus = 256;
+  }
+  return g_cus;
+}
+
+// ------------------------------------------------------------ combine ------
+// out[r] = (acc ? out[r] : 0) + sum_s coef[r][s] in[s]   (complex coefficients)
+__global__ __launch_bounds__(GT) void combine_kernel(const double* __restrict__ in, long long in_stride, int n_in,
+                                                     double* __restrict__ out, long long out_stride, int n_out,
+                                                     const double* __restrict__ coef, int coef_ld, int acc,
+                                                     long long n_c, long long dd) {
+  for (long long c = blockIdx.x * static_cast<long long>(GT) + threadIdx.x; c < n_c;
+       c += static_cast<long long>(gridDim.x) * GT) {
+    const long long mat = c / dd, e = c - mat * dd;
+    const long long off = mat * 2 * dd + e;
+    double xr[16], xi[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      if (s < n_in) {
+        xr[s] = in[s * in_stride + off];
+        xi[s] = in[s * in_stride + off + dd];
+      } else {
+        xr[s] = 0.0;
+        xi[s] = 0.0;
+      }
+    }
+    for (int r = 0; r < n_out; ++r) {
+      double ar = 0.0, ai = 0.0;
+      if (acc) {
+        ar = out[r * out_stride + off];
+        ai = out[r * out_stride + off + dd];
+      }
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        if (s < n_in) {
+          const double cr = coef[2 * (r * coef_ld + s)], ci = coef[2 * (r * coef_ld + s) + 1];
+          ar += cr * xr[s] - ci * xi[s];
+          ai += cr * xi[s] + ci * xr[s];
+        }
+      }
+      out[r * out_stride + off] = ar;
+      out[r * out_stride + off + dd] = ai;
+    }
+  }
+}
+
+// ---------------------------------------------------------- gemm_grad ------
+// partial[blockIdx.x][i][j] += Re(f * sum_items (u z^T - z^T u)[i][j]).
+// Workgroup: 16 x 16 threads, thread (ti, tj) owns outputs i = ti + 16a,
+// j = tj + 16b (a, b < NB).  f * u is staged in LDS (DP x (DP+1), zero padded),
+// z passes through LDS in 16-column (u z^T) and 16-row (z^T u) slabs.
+template <int NB>
+__global__ __launch_bounds__(GT) void gemm_grad_kernel(const double* __restrict__ u, const double* __restrict__ z,
+                                                       long long n_items, int d, double f_re, double f_im,
+                                                       double* __restrict__ partial) {
+  constexpr int DP = 16 * NB;
+  constexpr int LD = DP + 1;
+  HIP_DYNAMIC_SHARED(double, lds);
+  double* fur = lds;
+  double* fui = fur + DP * LD;
+  double* zr = fui + DP * LD;
+  constexpr int ZB = (DP * 17 > 16 * LD) ? DP * 17 : 16 * LD;
+  double* zi = zr + ZB;
+  const int tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
+  const long long dd = static_cast<long long>(d) * d;
+  double acc[NB][NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[a][b] = 0.0;
+  for (int e = tid; e < DP * LD; e += GT) {
+    fur[e] = 0.0;
+    fui[e] = 0.0;
+  }
+  for (long long it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const double* U = u + it * 2 * dd;
+    const double* Z = z + it * 2 * dd;
+    __syncthreads();
+    for (int e = tid; e < d * d; e += GT) {
+      const int x = e / d, y = e - x * d;
+      const double ur = U[e], ui = U[e + dd];
+      fur[x * LD + y] = f_re * ur - f_im * ui;
+      fui[x * LD + y] = f_re * ui + f_im * ur;
+    }
+    // u z^T: sum over columns c
+    for (int c0 = 0; c0 < d; c0 += 16) {
+      __syncthreads();
+      for (int e = tid; e < DP * 16; e += GT) {
+        const int j = e / 16, cc = e - j * 16, c = c0 + cc;
+        double vr = 0.0, vi = 0.0;
+        if (j < d && c < d) {
+          vr = Z[j * d + c];
+          vi = Z[j * d + c + dd];
+        }
+        zr[j * 17 + cc] = vr;
+        zi[j * 17 + cc] = vi;
+      }
+      __syncthreads();
+      const int cm = min(16, d - c0);
+      for (int cc = 0; cc < cm; ++cc) {
+        double ar[NB], ai[NB], br[NB], bi[NB];
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+          ar[a] = fur[(ti + 16 * a) * LD + c0 + cc];
+          ai[a] = fui[(ti + 16 * a) * LD + c0 + cc];
+          br[a] = zr[(tj + 16 * a) * 17 + cc];
+          bi[a] = zi[(tj + 16 * a) * 17 + cc];
+        }
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+          for (int b = 0; b < NB; ++b) acc[a][b] += ar[a] * br[b] - ai[a] * bi[b];
+      }
+    }
+    // - z^T u: sum over rows x
+    for (int x0 = 0; x0 < d; x0 += 16) {
+      __syncthreads();
+      for (int e = tid; e < 16 * DP; e += GT) {
+        const int xx = e / DP, i = e - xx * DP, x = x0 + xx;
+        double vr = 0.0, vi = 0.0;
+        if (x < d && i < d) {
+          vr = Z[x * d + i];
+          vi = Z[x * d + i + dd];
+        }
+        zr[xx * LD + i] = vr;
+        zi[xx * LD + i] = vi;
+      }
+      __syncthreads();
+      const int xm = min(16, d - x0);
+      for (int xx = 0; xx < xm; ++xx) {
+        double ar[NB], ai[NB], br[NB], bi[NB];
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+          ar[a] = zr[xx * LD + ti + 16 * a];
+          ai[a] = zi[xx * LD + ti + 16 * a];
+          br[a] = fur[(x0 + xx) * LD + tj + 16 * a];
+          bi[a] = fui[(x0 + xx) * LD + tj + 16 * a];
+        }
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+          for (int b = 0; b < NB; ++b) acc[a][b] -= ar[a] * br[b] - ai[a] * bi[b];
+      }
+    }
+  }
+  double* P = partial + static_cast<long long>(blockIdx.x) * dd;
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int i = ti + 16 * a, j = tj + 16 * b;
+      if (i < d && j < d) P[i * d + j] += acc[a][b];
+    }
+}
+
+template <int NB>
+size_t gemm_grad_lds() {
+  constexpr int DP = 16 * NB, LD = DP + 1;
+  constexpr int ZB = (DP * 17 > 16 * LD) ? DP * 17 : 16 * LD;
+  return sizeof(double) * (2 * DP * LD + 2 * ZB);
+}
+
+__global__ void reduce_parts_kernel(const double* __restrict__ partial, int n_parts, long long len,
+                                    double* __restrict__ out) {
+  const long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x;
+  if (i >= len) return;
+  double s = 0.0;
+  for (int p = 0; p < n_parts; ++p) s += partial[p * len + i];
+  out[i] += s;
+}
+
+// ------------------------------------------------------------ nb_grad ------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline int digit_row(int a, int r, int ds, int S) {
+  // product index with mode-s digit a and remaining digits r = hi * S + lo
+  const int hi = r / S, lo = r - hi * S;
+  return (hi * ds + a) * S + lo;
+}
+
+// One launch per mode s.  Thread t < G * ds (G = GT / ds) owns digit
+// delta = t / G of mode s and accumulates TL[.][delta] and TR[delta][.]
+// over all its items; lower-neighbour pairings and <u, z> are reduced per item.
+__global__ __launch_bounds__(GT) void nb_grad_kernel(GradOps g, int s, const double* __restrict__ u,
+                                                     const double* __restrict__ z, long long n_items,
+                                                     double* __restrict__ gv, double* __restrict__ gc,
+                                                     double* __restrict__ gnu) {
+  HIP_DYNAMIC_SHARED(double, lds);
+  const int d = g.d, ds = g.dims[s], S = g.strides[s], LD = d + 1;
+  const long long dd = static_cast<long long>(d) * d;
+  double* sur = lds;
+  double* sui = sur + d * LD;
+  double* sv = sui + d * LD;                                   // ds * ds
+  double* red = sv + MAXDS * MAXDS;                            // 4 waves x (4 MAXDOWN + 2)
+  int* qi = reinterpret_cast<int*>(red + 4 * (4 * MAXDOWN + 2));  // per item: idx, term, count
+  double* qa = reinterpret_cast<double*>(qi + 4 * MAXQ);          // aL re, aL im
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int G = GT / ds;
+  const bool active = tid < G * ds;
+  const int delta = active ? tid / G : 0, gi = tid % G;
+  const int R = d / ds;
+  for (int e = tid; e < ds * ds; e += GT) sv[e] = g.v[g.v_off[s] + e];
+  double TL[MAXDS], TR[MAXDS];
+#pragma unroll
+  for (int a = 0; a < MAXDS; ++a) {
+    TL[a] = 0.0;
+    TR[a] = 0.0;
+  }
+  for (long long it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const long long traj = it / g.n_ado;
+    const int n = static_cast<int>(it - traj * g.n_ado);
+    const double* U = u + it * 2 * dd;
+    const double* Zt = z + traj * g.n_ado * 2 * dd;
+    __syncthreads();
+    for (int e = tid; e < d * d; e += GT) {
+      const int x = e / d, y = e - x * d;
+      sur[x * LD + y] = U[e];
+      sui[x * LD + y] = U[e + dd];
+    }
+    const int q0 = g.nb_ptr[n * g.n_modes + s];
+    const int nq = min(g.nb_ptr[n * g.n_modes + s + 1] - q0, MAXQ);
+    if (tid < nq) {
+      qi[4 * tid] = g.nb_idx[q0 + tid];
+      qi[4 * tid + 1] = g.nb_tj[2 * (q0 + tid)];
+      qi[4 * tid + 2] = g.nb_tj[2 * (q0 + tid) + 1];
+      qa[2 * tid] = g.nb_a[4 * (q0 + tid)];
+      qa[2 * tid + 1] = g.nb_a[4 * (q0 + tid) + 1];
+    }
+    __syncthreads();
+    double pLr[MAXDOWN], pLi[MAXDOWN], pRr[MAXDOWN], pRi[MAXDOWN];
+#pragma unroll
+    for (int k = 0; k < MAXDOWN; ++k) pLr[k] = pLi[k] = pRr[k] = pRi[k] = 0.0;
+    double Pr = 0.0, Pi = 0.0;
+    if (active) {
+      // TL pass: zeta elements with row digit delta
+      for (int e = gi; e < R * d; e += G) {
+        const int r = e / d, y = e - r * d;
+        const int x = digit_row(delta, r, ds, S);
+        double uar[MAXDS], uai[MAXDS];
+        double vur = 0.0, vui = 0.0;
+#pragma unroll
+        for (int a = 0; a < MAXDS; ++a) {
+          if (a < ds) {
+            const int xa = digit_row(a, r, ds, S);
+            uar[a] = sur[xa * LD + y];
+            uai[a] = sui[xa * LD + y];
+            const double va = sv[delta * ds + a];
+            vur += va * uar[a];
+            vui += va * uai[a];
+          } else {
+            uar[a] = 0.0;
+            uai[a] = 0.0;
+          }
+        }
+        double zLr = 0.0, zLi = 0.0;
+        int kd = 0;
+        for (int q = 0; q < nq; ++q) {
+          const double* Zm = Zt + static_cast<long long>(qi[4 * q]) * 2 * dd;
+          const double zr_ = Zm[x * d + y], zi_ = Zm[x * d + y + dd];
+          const double cr = qa[2 * q], ci = qa[2 * q + 1];
+          zLr += cr * zr_ - ci * zi_;
+          zLi += cr * zi_ + ci * zr_;
+          if (qi[4 * q + 2] > 0) {
+#pragma unroll
+            for (int k = 0; k < MAXDOWN; ++k)
+              if (k == kd) {
+                pLr[k] += vur * zr_ - vui * zi_;
+                pLi[k] += vur * zi_ + vui * zr_;
+              }
+            ++kd;
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < MAXDS; ++a) TL[a] += uar[a] * zLi + uai[a] * zLr;
+        if (s == 0) {
+          const double* Zn = Zt + static_cast<long long>(n) * 2 * dd;
+          const double zr_ = Zn[x * d + y], zi_ = Zn[x * d + y + dd];
+          double ur_ = 0.0, ui_ = 0.0;
+#pragma unroll
+          for (int a = 0; a < MAXDS; ++a)
+            if (a == delta) {
+              ur_ = uar[a];
+              ui_ = uai[a];
+            }
+          Pr += ur_ * zr_ - ui_ * zi_;
+          Pi += ur_ * zi_ + ui_ * zr_;
+        }
+      }
+      // TR pass: zeta elements with column digit delta
+      for (int e = gi; e < d * R; e += G) {
+        const int x = e / R, r = e - x * R;
+        const int y = digit_row(delta, r, ds, S);
+        double ubr[MAXDS], ubi[MAXDS];
+        double uvr = 0.0, uvi = 0.0;
+#pragma unroll
+        for (int a = 0; a < MAXDS; ++a) {
+          if (a < ds) {
+            const int ya = digit_row(a, r, ds, S);
+            ubr[a] = sur[x * LD + ya];
+            ubi[a] = sui[x * LD + ya];
+            const double va = sv[a * ds + delta];
+            uvr += ubr[a] * va;
+            uvi += ubi[a] * va;
+          } else {
+            ubr[a] = 0.0;
+            ubi[a] = 0.0;
+          }
+        }
+        double zRr = 0.0, zRi = 0.0;
+        int kd = 0;
+        for (int q = 0; q < nq; ++q) {
+          const double* Zm = Zt + static_cast<long long>(qi[4 * q]) * 2 * dd;
+          const double zr_ = Zm[x * d + y], zi_ = Zm[x * d + y + dd];
+          const double cr = qa[2 * q], ci = -qa[2 * q + 1];
+          zRr += cr * zr_ - ci * zi_;
+          zRi += cr * zi_ + ci * zr_;
+          if (qi[4 * q + 2] > 0) {
+#pragma unroll
+            for (int k = 0; k < MAXDOWN; ++k)
+              if (k == kd) {
+                pRr[k] += uvr * zr_ - uvi * zi_;
+                pRi[k] += uvr * zi_ + uvi * zr_;
+              }
+            ++kd;
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < MAXDS; ++a) TR[a] += zRr * ubi[a] + zRi * ubr[a];
+      }
+    }
+    // per-item reduction of the lower-neighbour pairings and <u_n, z_n>
+    constexpr int NV = 4 * MAXDOWN + 2;
+    double vals[NV];
+#pragma unroll
+    for (int k = 0; k < MAXDOWN; ++k) {
+      vals[4 * k] = pLr[k];
+      vals[4 * k + 1] = pLi[k];
+      vals[4 * k + 2] = pRr[k];
+      vals[4 * k + 3] = pRi[k];
+    }
+    vals[NV - 2] = Pr;
+    vals[NV - 1] = Pi;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) vals[k] = wave_sum(vals[k]);
+    if (lane == 0)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) red[wave * NV + k] = vals[k];
+    __syncthreads();
+    if (tid == 0) {
+      double tot[NV];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) tot[k] = red[k] + red[NV + k] + red[2 * NV + k] + red[3 * NV + k];
+      int kd = 0;
+      for (int q = 0; q < nq && kd < MAXDOWN; ++q) {
+        const int cnt = qi[4 * q + 2];
+        if (cnt > 0) {
+          const int j = qi[4 * q + 1];
+          const double lr = tot[4 * kd], li = tot[4 * kd + 1], rr = tot[4 * kd + 2], ri = tot[4 * kd + 3];
+          atomicAdd(&gc[2 * j], cnt * (li - ri));
+          atomicAdd(&gc[2 * j + 1], cnt * (lr + rr));
+          ++kd;
+        }
+      }
+      if (s == 0) {
+        for (int j = 0; j < g.n_terms; ++j) {
+          const int cnt = g.ado_n[static_cast<long long>(n) * g.n_terms + j];
+          if (cnt > 0) atomicAdd(&gnu[j], -cnt * tot[NV - 2]);
+        }
+      }
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int a = 0; a < MAXDS; ++a) {
+      if (a < ds) {
+        atomicAdd(&gv[a * ds + delta], TL[a]);
+        atomicAdd(&gv[delta * ds + a], -TR[a]);
+      }
+    }
+  }
+}
+
+size_t nb_grad_lds(int d) {
+  return sizeof(double) * (2 * static_cast<size_t>(d) * (d + 1) + MAXDS * MAXDS + 4 * (4 * MAXDOWN + 2)) +
+         sizeof(int) * 4 * MAXQ + sizeof(double) * 2 * MAXQ + 64;
+}
+
+}  // namespace
+
+int grad_max_parts() { return 1024; }
+
+bool grad_supported(int d, const int* dims, int n_modes, int max_terms_per_mode) {
+  if (d > 80) return false;
+  for (int s = 0; s < n_modes; ++s)
+    if (dims[s] > MAXDS) return false;
+  return 2 * max_terms_per_mode <= MAXQ && max_terms_per_mode <= MAXDOWN;
+}
+
+void launch_combine(const double* in, long long in_stride, int n_in, double* out, long long out_stride, int n_out,
+                    const double* coef_dev, int accumulate, long long n_mats, int d, hipStream_t stream) {
+  const long long dd = static_cast<long long>(d) * d;
+  const long long n_c = n_mats * dd;
+  const int blocks = static_cast<int>(std::min<long long>((n_c + GT - 1) / GT, 65536));
+  for (int s0 = 0; s0 < n_in; s0 += 16) {
+    const int k = std::min(16, n_in - s0);
+    hipLaunchKernelGGL(combine_kernel, dim3(blocks), dim3(GT), 0, stream, in + s0 * in_stride, in_stride, k, out,
+                       out_stride, n_out, coef_dev + 2 * s0, n_in, (s0 > 0 || accumulate) ? 1 : 0, n_c, dd);
+  }
+  check("combine kernel");
+}
+
+template <int NB>
+void gemm_grad_nb(const double* u, const double* z, long long n_items, int d, double fr, double fi,
+                  double* partial, hipStream_t stream) {
+  const size_t lds = gemm_grad_lds<NB>();
+  static bool attr = false;
+  if (!attr) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_grad_kernel<NB>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
+      throw std::runtime_error("gemm_grad: LDS attribute");
+    attr = true;
+  }
+  const long long per_cu = std::max<long long>(1, (160 * 1024) / static_cast<long long>(lds));
+  const long long grid = std::min<long long>({n_items, cus() * per_cu, grad_max_parts()});
+  if (grid <= 0) return;
+  hipLaunchKernelGGL((gemm_grad_kernel<NB>), dim3(static_cast<unsigned>(grid)), dim3(GT), lds, stream, u, z,
+                     n_items, d, fr, fi, partial);
+  check("gemm_grad kernel");
+}
+
+void launch_gemm_grad(const double* u, const double* z, long long n_items, int d, double f_re, double f_im,
+                      double* partial, hipStream_t stream) {
+  switch ((d + 15) / 16) {
+    case 1: gemm_grad_nb<1>(u, z, n_items, d, f_re, f_im, partial, stream); break;
+    case 2: gemm_grad_nb<2>(u, z, n_items, d, f_re, f_im, partial, stream); break;
+    case 3: gemm_grad_nb<3>(u, z, n_items, d, f_re, f_im, partial, stream); break;
+    case 4: gemm_grad_nb<4>(u, z, n_items, d, f_re, f_im, partial, stream); break;
+    case 5: gemm_grad_nb<5>(u, z, n_items, d, f_re, f_im, partial, stream); break;
+    default: throw std::runtime_error("gemm_grad: d > 80");
+  }
+}
+
+void launch_reduce_parts(const double* partial, int n_parts, long long len, double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(static_cast<unsigned>((len + 255) / 256)), dim3(256), 0, stream,
+                     partial, n_parts, len, out);
+  check("reduce kernel");
+}
+
+void launch_nb_grad(const GradOps& g, int s, const double* u, const double* z, long long n_items, double* gv_s,
+                    double* gc, double* gnu, hipStream_t stream) {
+  const size_t lds = nb_grad_lds(g.d);
+  static size_t attr = 0;
+  if (lds > attr) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&nb_grad_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
+      throw std::runtime_error("nb_grad: LDS attribute");
+    attr = lds;
+  }
+  const long long per_cu = std::max<long long>(1, (160 * 1024) / static_cast<long long>(lds));
+  const long long grid = std::min<long long>(n_items, cus() * per_cu);
+  if (grid <= 0) return;
+  hipLaunchKernelGGL(nb_grad_kernel, dim3(static_cast<unsigned>(grid)), dim3(GT), lds, stream, g, s, u, z, n_items,
+                     gv_s, gc, gnu);
+  check("nb_grad kernel");
+}
+
+}  // namespace heom

@@ -19,6 +19,9 @@ struct Neighbours {
   // through mode s's coupling operator V_s as  -i (aL V_s rho_m - aR rho_m V_s).
   std::vector<int> ptr, idx;
   std::vector<cplx> aL, aR;
+  // per entry: (term j, n_j of ADO `ado`) for a lower neighbour n - e_j, (j, 0)
+  // for an upper neighbour n + e_j
+  std::vector<int> tj;
 };
 
 struct HostModel {

@@ -374,6 +374,8 @@ HostModel build_host_model(const heom_params& p) {
           auto it = index.find(key_of(n));
           if (it != index.end()) {
             nb.idx.push_back(it->second);
+            nb.tj.push_back(j);
+            nb.tj.push_back(0);
             if (!adjoint) {
               nb.aL.push_back(1.0);
               nb.aR.push_back(1.0);
@@ -386,6 +388,8 @@ HostModel build_host_model(const heom_params& p) {
           if (nj > 0) {
             n[j] = nj - 1;
             nb.idx.push_back(index.at(key_of(n)));
+            nb.tj.push_back(j);
+            nb.tj.push_back(nj);
             if (!adjoint) {
               nb.aL.push_back(static_cast<double>(nj) * hm.c[j]);
               nb.aR.push_back(static_cast<double>(nj) * std::conj(hm.c[j]));

@@ -74,6 +74,12 @@ class heom_grid(C.Structure):
                 ("n_t2", C.c_int), ("t2_steps", C.POINTER(C.c_int))]
 
 
+class heom_op_grad(C.Structure):
+    _fields_ = [("dH", C.c_void_p), ("dv", C.c_void_p), ("dmu", C.c_void_p), ("dc", C.c_void_p),
+                ("dnu", C.c_void_p), ("stationary_steps", C.c_int),
+                ("stationary_residual", C.c_double)]
+
+
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 _FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
@@ -110,6 +116,11 @@ _SIGS = {
                                    C.c_int, C.c_int, C.c_void_p]),
     "heom_spectrum_2d": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_double,
                                    C.c_void_p]),
+    "heom_response_2d_vjp": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(heom_grid), C.c_void_p,
+                                       C.c_int, C.c_double, C.c_int, C.POINTER(heom_op_grad)]),
+    "heom_spectrum_2d_vjp": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_void_p]),
+    "heom_params_vjp": (C.c_int, [C.POINTER(heom_params), C.c_void_p, C.c_int, C.c_double,
+                                  C.POINTER(heom_op_grad), C.c_void_p]),
     "heom_batch_create": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]),
     "heom_batch_free": (None, [C.c_void_p]),
     "heom_batch_propagate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int]),
@@ -399,6 +410,75 @@ def heom_spectrum_2d(R_I, R_II, dt_s):
     S = np.zeros((2 * n3, 2 * n1))
     _check(load_library().heom_spectrum_2d(_ptr(R_I), _ptr(R_II), n1, n3, float(dt_s), _ptr(S)))
     return S
+
+
+def _grid_struct(grid):
+    t2 = (C.c_int * len(grid["t2_steps"]))(*[int(x) for x in grid["t2_steps"]])
+    g = heom_grid(int(grid["n1"]), int(grid["n3"]), int(grid["steps_per_sample"]),
+                  len(grid["t2_steps"]), t2)
+    return g, t2
+
+
+def _grad_arrays(d, dims, M):
+    return {"H": np.zeros((d, d)), "v": np.zeros(sum(x * x for x in dims)), "mu": np.zeros((d, d)),
+            "c": np.zeros((M, 2)), "nu": np.zeros(M)}
+
+
+def _grad_struct(a):
+    g = heom_op_grad()
+    g.dH, g.dv, g.dmu = a["H"].ctypes.data, a["v"].ctypes.data, a["mu"].ctypes.data
+    g.dc, g.dnu = a["c"].ctypes.data, a["nu"].ctypes.data
+    return g
+
+
+def heom_response_2d_vjp(model, rho_eq, grid, W, stationary=True, tol=1e-10, max_steps=1000000):
+    """Operator gradients of J = Re sum W R (W: complex [n_t2][2][n1][n3]).
+
+    Returns a dict: H (d x d), v (list of d_s x d_s), mu (d x d), c (n_terms x 2:
+    d/dRe c_j, d/dIm c_j), nu (n_terms), stationary_steps, stationary_residual."""
+    g, keep = _grid_struct(grid)
+    Wi = np.zeros(W.size * 2)
+    Wi[0::2] = np.real(W).ravel()
+    Wi[1::2] = np.imag(W).ravel()
+    a = _grad_arrays(model.d, model.dims, model.n_terms)
+    st = _grad_struct(a)
+    _check(_lib.heom_response_2d_vjp(model.handle, rho_eq.handle, C.byref(g), _ptr(Wi),
+                                     int(bool(stationary)), float(tol), int(max_steps), C.byref(st)))
+    vs, off = [], 0
+    for ds in model.dims:
+        vs.append(a["v"][off:off + ds * ds].reshape(ds, ds).copy())
+        off += ds * ds
+    return {"H": a["H"], "v": vs, "mu": a["mu"], "c": a["c"], "nu": a["nu"],
+            "stationary_steps": st.stationary_steps, "stationary_residual": st.stationary_residual}
+
+
+def heom_spectrum_2d_vjp(G, n1, n3, dt_s):
+    """W[P][j][k] (complex, P = I, II) with sum G S_C(R_I, R_II) = Re sum W R."""
+    load_library()
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    if G.shape != (2 * n3, 2 * n1):
+        raise ValueError("G must have shape (2 n3, 2 n1)")
+    out = np.zeros(2 * n1 * n3 * 2)
+    _check(_lib.heom_spectrum_2d_vjp(_ptr(G), int(n1), int(n3), float(dt_s), _ptr(out)))
+    return (out[0::2] + 1j * out[1::2]).reshape(2, n1, n3)
+
+
+def heom_params_vjp(params, dirs, grad, step=1e-6):
+    """out[i] = <grad, d(operators)/d(params) along dirs[i]> (host)."""
+    load_library()
+    p, keep = _params_struct(params)
+    structs = [_params_struct(x) for x in dirs]
+    arr = (heom_params * max(1, len(dirs)))(*[x[0] for x in structs])
+    a = {"H": np.ascontiguousarray(grad["H"], dtype=np.float64),
+         "v": np.ascontiguousarray(np.concatenate([np.ravel(x) for x in grad["v"]]), dtype=np.float64),
+         "mu": np.ascontiguousarray(grad["mu"], dtype=np.float64),
+         "c": np.ascontiguousarray(grad["c"], dtype=np.float64),
+         "nu": np.ascontiguousarray(grad["nu"], dtype=np.float64)}
+    st = _grad_struct(a)
+    out = np.zeros(len(dirs))
+    _check(_lib.heom_params_vjp(C.byref(p), C.cast(arr, C.c_void_p), len(dirs), float(step),
+                                C.byref(st), _ptr(out)))
+    return out
 
 
 class Batch:

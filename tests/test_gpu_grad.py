@@ -1,0 +1,182 @@
+"""GPU parity of the reverse-mode gradient (heom_response_2d_vjp and the
+chain to the fitted parameters) against central finite differences of the
+CPU FP64 oracle.
+
+Tolerance: the oracle's central differences (step 1e-6 on operators, 1e-5
+relative on parameters) carry truncation errors of order step^2 times third
+derivatives and rounding of order 1e-16/step, i.e. about 1e-9..1e-7 of the
+largest gradient entry; the adjoint is exact for the discrete RK4 propagator.
+The bar is 1e-6 of the largest entry for operator gradients and 1e-5 for the
+parameter gradient (which also goes through the spectrum and the build).
+"""
+
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import gradient as og
+from oracle import heom as oh
+from oracle import model as om
+
+P = pytest.importorskip("paper_2601_20550_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _maxabs(g):
+    return max(np.max(np.abs(g["H"])), np.max(np.abs(g["mu"])), np.max(np.abs(g["c"])),
+               np.max(np.abs(g["nu"])), max(np.max(np.abs(v)) for v in g["v"]))
+
+
+def _compare(got, ref, tol):
+    scale = _maxabs(ref)
+    assert scale > 0
+    for k in ("H", "mu", "c", "nu"):
+        err = np.max(np.abs(np.asarray(got[k]) - ref[k]))
+        assert err < tol * scale, (k, err, scale)
+    for s, (a, b) in enumerate(zip(got["v"], ref["v"])):
+        err = np.max(np.abs(a - b))
+        assert err < tol * scale, ("v", s, err, scale)
+
+
+def _random_W(grid, seed):
+    rng = np.random.default_rng(seed)
+    shape = (len(grid["t2_steps"]), 2, grid["n1"], grid["n3"])
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+@pytest.fixture(scope="module")
+def small():
+    params, grid, theta_t = w.cfg5_small()
+    o = om.build(params)
+    rho = oh.stationary_state(o)
+    return params, grid, theta_t, o, rho
+
+
+@pytest.mark.parametrize("stationary", [False, True])
+def test_vjp_operator_gradients(small, stationary):
+    params, grid, _, o, rho = small
+    W = _random_W(grid, 21)
+    m = P.heom_model_build(params)
+    r = P.State(m, 1, "fp64")
+    r.upload(rho[None])
+    got = P.heom_response_2d_vjp(m, r, grid, W, stationary=stationary, tol=1e-13)
+    ref = og.operator_gradient_fd(o, rho, grid, W, stationary=stationary)
+    _compare(got, ref, 1e-6)
+    if stationary:
+        assert got["stationary_steps"] > 0 and got["stationary_residual"] <= 1e-13
+
+
+def test_vjp_single_t2_and_single_sample_edges(small):
+    params, _, _, o, rho = small
+    m = P.heom_model_build(params)
+    r = P.State(m, 1, "fp64")
+    r.upload(rho[None])
+    for grid in ({"n1": 1, "n3": 3, "steps_per_sample": 2, "t2_steps": [0]},
+                 {"n1": 3, "n3": 1, "steps_per_sample": 2, "t2_steps": [5]},
+                 {"n1": 2, "n3": 2, "steps_per_sample": 3, "t2_steps": [0, 0, 17]}):
+        W = _random_W(grid, 5)
+        got = P.heom_response_2d_vjp(m, r, grid, W, stationary=False)
+        ref = og.operator_gradient_fd(o, rho, grid, W, stationary=False)
+        _compare(got, ref, 1e-6)
+
+
+def test_parameter_gradient_end_to_end(small):
+    params, grid, theta_t, o, rho = small
+    _, _, _, S_t = og.spectra(w.apply_theta(params, theta_t), grid)
+    ref = og.loss_gradient_fd(params, grid, S_t, w.apply_theta, w.theta_size(params))
+    m = P.heom_model_build(params)
+    r = P.State(m, 1, "fp64")
+    r.upload(rho[None])
+    R = P.heom_response_2d(m, r, grid, "fp64", "adjoint")
+    dt_s = grid["steps_per_sample"] * params["dt"]
+    W = np.zeros_like(R)
+    for q in range(R.shape[0]):
+        S = P.heom_spectrum_2d(R[q, 0], R[q, 1], dt_s)
+        W[q] = P.heom_spectrum_2d_vjp(2.0 * (S - S_t[q]), grid["n1"], grid["n3"], dt_s)
+    g = P.heom_response_2d_vjp(m, r, grid, W, stationary=True, tol=1e-13)
+    got = P.heom_params_vjp(params, w.theta_directions(params), g)
+    assert np.max(np.abs(got - ref)) < 1e-5 * np.max(np.abs(ref))
+
+
+def _fd_entry(o, rho, grid, W, make, step=1e-6):
+    return (og.objective(make(step), rho, grid, W) - og.objective(make(-step), rho, grid, W)) / (2 * step)
+
+
+def test_vjp_three_modes_sampled_entries():
+    # d = 80 (4 x 4 x 5), nine exponential terms, depth 1: sampled operator
+    # entries against single central differences of the oracle
+    params = w.cfg3()[0]
+    params["depth"] = 1
+    o = om.build(params)
+    rho = oh.propagate(o, oh.ground_state_hierarchy(o), 20)
+    grid = {"n1": 3, "n3": 3, "steps_per_sample": 3, "t2_steps": [0, 4]}
+    W = _random_W(grid, 8)
+    m = P.heom_model_build(params)
+    r = P.State(m, 1, "fp64")
+    r.upload(rho[None])
+    got = P.heom_response_2d_vjp(m, r, grid, W, stationary=False)
+    d = o.d
+    checks = []
+    for (a, b) in ((0, 1), (5, 7), (79, 2), (33, 33)):
+        E = np.zeros((d, d))
+        E[a, b] = 1.0
+        checks.append((got["H"][a, b], lambda e, E=E: replace(o, H=o.H + e * E)))
+    for (a, b) in ((1, 0), (4, 20), (0, 16)):
+        E = np.zeros((d, d))
+        E[a, b] = 1.0
+
+        def mk(e, E=E):
+            mu = o.mu + e * E
+            N = om.quanta(o.dims)
+            mp = np.where(N[:, None] > N[None, :], mu, 0.0)
+            return replace(o, mu=mu, mu_plus=mp, mu_minus=mp.T.copy())
+        checks.append((got["mu"][a, b], mk))
+    for s, (a, b) in ((0, (1, 2)), (2, (0, 4)), (1, (3, 3))):
+        E = np.zeros((o.dims[s], o.dims[s]))
+        E[a, b] = 1.0
+        dV = om.embed({s: E}, o.dims)
+
+        def mk(e, s=s, dV=dV):
+            V = list(o.V)
+            V[s] = V[s] + e * dV
+            return replace(o, V=V)
+        checks.append((got["v"][s][a, b], mk))
+    for j in (0, 4, 8):
+        for part, z in ((0, 1.0), (1, 1j)):
+            def mk(e, j=j, z=z):
+                c = o.c.copy()
+                c[j] += e * z
+                return replace(o, c=c)
+            checks.append((got["c"][j, part], mk))
+
+        def mkn(e, j=j):
+            nu = o.nu.copy()
+            nu[j] += e
+            return replace(o, nu=nu)
+        checks.append((got["nu"][j], mkn))
+    ref = np.array([_fd_entry(o, rho, grid, W, mk) for _, mk in checks])
+    val = np.array([g for g, _ in checks])
+    scale = max(np.max(np.abs(ref)), _maxabs(got) * 1e-3)
+    assert np.max(np.abs(val - ref)) < 1e-6 * scale, (val, ref)
+
+
+def test_vjp_rejects_unsupported_models():
+    params = w.cfg1()[0]
+    params["modes"][0]["n_keep"] = 9          # single-mode dimension 9 > 8
+    m = P.heom_model_build(params)
+    r = P.State(m, 1, "fp64")
+    r.set_ground()
+    grid = {"n1": 2, "n3": 2, "steps_per_sample": 1, "t2_steps": [0]}
+    with pytest.raises(P.heom2dvs.HeomError) as e:
+        P.heom_response_2d_vjp(m, r, grid, _random_W(grid, 1))
+    assert e.value.code == P.heom2dvs.HEOM_ERR_PARAM

@@ -107,3 +107,29 @@ def test_invalid_parameters_rejected():
 
     for f in (keep_gt_basis, bad_coupling, pole, neg_dt, too_big):
         assert _bad(f) == P.heom2dvs.HEOM_ERR_PARAM
+
+
+def test_spectrum_vjp_matches_oracle():
+    from oracle import gradient as og
+    rng = np.random.default_rng(5)
+    for n1, n3, dt_s in ((6, 6, 0.4), (5, 7, 1.0)):
+        G = rng.standard_normal((2 * n3, 2 * n1))
+        got = P.heom_spectrum_2d_vjp(G, n1, n3, dt_s)
+        ref = og.spectrum_vjp(G, n1, n3, dt_s)
+        assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_params_vjp_matches_oracle_directions():
+    # the chain from operator gradients to the fitted factors, with the build's
+    # derivative taken from the C++ builder, equals the oracle's contraction
+    from oracle import gradient as og
+    params, _, _ = w.cfg5_small()
+    o = om.build(params)
+    rng = np.random.default_rng(9)
+    g = {"H": rng.standard_normal((o.d, o.d)), "mu": rng.standard_normal((o.d, o.d)),
+         "v": [rng.standard_normal((ds, ds)) for ds in o.dims],
+         "c": rng.standard_normal((len(o.nu), 2)), "nu": rng.standard_normal(len(o.nu))}
+    dirs = w.theta_directions(params)
+    got = P.heom_params_vjp(params, dirs, g)
+    ref = np.array([og.contract(g, og.operator_directions_fd(params, dr)) for dr in dirs])
+    assert np.max(np.abs(got - ref)) < 1e-7 * np.max(np.abs(ref))
