@@ -259,8 +259,9 @@ typedef struct {
  * propagation until the series term falls below tol x its first term (at most
  * max_steps; stationary_steps / stationary_residual report it;
  * HEOM_ERR_NOCONV if not reached); 0: rho_eq is held fixed.  W: host
- * [n_t2][2][n1][n3] complex.  Needs d <= 80, every mode dimension <= 8 and
- * K + 1 <= 4 terms per mode (HEOM_ERR_PARAM otherwise). */
+ * [n_t2][2][n1][n3] complex.  Needs d <= 80, every mode dimension d_s <= 8
+ * with d_s * d <= 512, and K + 1 <= 4 terms per mode (HEOM_ERR_PARAM
+ * otherwise). */
 int heom_response_2d_vjp(heom_model* model, const heom_state* rho_eq, const heom_grid* grid, const double* W,
                          int rho_is_stationary, double tol, int max_steps, heom_op_grad* out);
 

@@ -1555,7 +1555,7 @@ int heom_response_2d_vjp(heom_model* m, const heom_state* rho_eq, const heom_gri
       kmax = std::max(kmax, k);
     }
     if (!heom::grad_supported(m->hm.d, m->hm.dims, m->hm.n_modes, kmax))
-      throw HeomError(HEOM_ERR_PARAM, "gradient needs d <= 80, mode dimensions <= 8 and <= 4 terms per mode");
+      throw HeomError(HEOM_ERR_PARAM, "gradient needs d <= 80, mode dimensions d_s <= 8 with d_s * d <= 512, and <= 4 terms per mode");
     response_vjp(m, rho_eq, g, W, rho_is_stationary != 0, tol, max_steps, out);
   });
 }

@@ -23,7 +23,7 @@ struct GradOps {
 };
 
 // Whether the gradient kernels support a model: d <= 80, every mode dimension
-// <= 8 and at most 4 exponential terms per mode.
+// d_s <= 8 with d_s * d <= 512, and at most 4 exponential terms per mode.
 bool grad_supported(int d, const int* dims, int n_modes, int max_terms_per_mode);
 int grad_max_parts();
 

@@ -231,44 +231,53 @@ __device__ inline int digit_row(int a, int r, int ds, int S) {
   return (hi * ds + a) * S + lo;
 }
 
-// One launch per mode s.  Thread t < G * ds (G = GT / ds) owns digit
-// delta = t / G of mode s and accumulates TL[.][delta] and TR[delta][.]
-// over all its items; lower-neighbour pairings and <u, z> are reduced per item.
-__global__ __launch_bounds__(GT) void nb_grad_kernel(GradOps g, int s, const double* __restrict__ u,
-                                                     const double* __restrict__ z, long long n_items,
-                                                     double* __restrict__ gv, double* __restrict__ gc,
-                                                     double* __restrict__ gnu) {
+// One launch per mode s (DS = its dimension), NT = 512 threads.  Thread
+// t < DS * d owns the row digit ap = t / d and the column y = t % d, whose
+// mode-s digit dc is then fixed too; it loops over the rest r of the row
+// index (x = (ap, r)), so every accumulator index is a compile-time constant:
+//   TL[a][ap]  += Im(u[(a,r)][y] zL[x][y])          (a < DS)
+//   TR[dc][a'] += Im(zR[x][y] u[x][(a',r_y)])       (a' < DS)
+// Each neighbour element is loaded once, coalesced along y.  Lower-neighbour
+// pairings and <u_n, z_n> are reduced per item; TL and TR once per
+// workgroup at the end.
+constexpr int NBT = 512;
+
+template <int DS>
+__global__ __launch_bounds__(NBT) void nb_grad_kernel(GradOps g, int s, const double* __restrict__ u,
+                                                      const double* __restrict__ z, long long n_items,
+                                                      double* __restrict__ gv, double* __restrict__ gc,
+                                                      double* __restrict__ gnu) {
   HIP_DYNAMIC_SHARED(double, lds);
-  const int d = g.d, ds = g.dims[s], S = g.strides[s], LD = d + 1;
+  constexpr int NV = 4 * MAXDOWN + 2;
+  constexpr int NW = NBT / 64;
+  const int d = g.d, S = g.strides[s], LD = d + 1;
   const long long dd = static_cast<long long>(d) * d;
   double* sur = lds;
   double* sui = sur + d * LD;
-  double* sv = sui + d * LD;                                   // ds * ds
-  double* red = sv + MAXDS * MAXDS;                            // 4 waves x (4 MAXDOWN + 2)
-  int* qi = reinterpret_cast<int*>(red + 4 * (4 * MAXDOWN + 2));  // per item: idx, term, count
-  double* qa = reinterpret_cast<double*>(qi + 4 * MAXQ);          // aL re, aL im
+  double* sv = sui + d * LD;                                   // DS * DS (<= MAXDS^2)
+  double* red = sv + MAXDS * MAXDS;                            // NW x NV
+  int* qi = reinterpret_cast<int*>(red + NW * NV);             // per item: idx, term, count
+  double* qa = reinterpret_cast<double*>(qi + 4 * MAXQ);       // aL re, aL im
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-  const int G = GT / ds;
-  const bool active = tid < G * ds;
-  const int delta = active ? tid / G : 0, gi = tid % G;
-  const int R = d / ds;
-  for (int e = tid; e < ds * ds; e += GT) sv[e] = g.v[g.v_off[s] + e];
-  double TL[MAXDS], TR[MAXDS];
+  const bool active = tid < DS * d;
+  const int ap = active ? tid / d : 0, y = active ? tid % d : 0;
+  const int R = d / DS;
+  const int hy = y / (DS * S), dc = (y / S) % DS, ly = y % S;
+  const int ry0 = hy * DS * S + ly;  // column index of y with mode-s digit 0
+  for (int e = tid; e < DS * DS; e += NBT) sv[e] = g.v[g.v_off[s] + e];
+  double TL[DS], TR[DS];
 #pragma unroll
-  for (int a = 0; a < MAXDS; ++a) {
-    TL[a] = 0.0;
-    TR[a] = 0.0;
-  }
+  for (int a = 0; a < DS; ++a) TL[a] = TR[a] = 0.0;
   for (long long it = blockIdx.x; it < n_items; it += gridDim.x) {
     const long long traj = it / g.n_ado;
     const int n = static_cast<int>(it - traj * g.n_ado);
     const double* U = u + it * 2 * dd;
     const double* Zt = z + traj * g.n_ado * 2 * dd;
     __syncthreads();
-    for (int e = tid; e < d * d; e += GT) {
-      const int x = e / d, y = e - x * d;
-      sur[x * LD + y] = U[e];
-      sui[x * LD + y] = U[e + dd];
+    for (int e = tid; e < d * d; e += NBT) {
+      const int x = e / d, yy = e - x * d;
+      sur[x * LD + yy] = U[e];
+      sui[x * LD + yy] = U[e + dd];
     }
     const int q0 = g.nb_ptr[n * g.n_modes + s];
     const int nq = min(g.nb_ptr[n * g.n_modes + s + 1] - q0, MAXQ);
@@ -285,27 +294,26 @@ __global__ __launch_bounds__(GT) void nb_grad_kernel(GradOps g, int s, const dou
     for (int k = 0; k < MAXDOWN; ++k) pLr[k] = pLi[k] = pRr[k] = pRi[k] = 0.0;
     double Pr = 0.0, Pi = 0.0;
     if (active) {
-      // TL pass: zeta elements with row digit delta
-      for (int e = gi; e < R * d; e += G) {
-        const int r = e / d, y = e - r * d;
-        const int x = digit_row(delta, r, ds, S);
-        double uar[MAXDS], uai[MAXDS];
-        double vur = 0.0, vui = 0.0;
+      for (int r = 0; r < R; ++r) {
+        const int hr = r / S, lr = r - hr * S;
+        const int xr0 = hr * DS * S + lr;  // row index with mode-s digit 0
+        const int x = xr0 + ap * S;
+        double vur = 0.0, vui = 0.0, uvr = 0.0, uvi = 0.0;
+        double uar[DS], uai[DS], ubr[DS], ubi[DS];
 #pragma unroll
-        for (int a = 0; a < MAXDS; ++a) {
-          if (a < ds) {
-            const int xa = digit_row(a, r, ds, S);
-            uar[a] = sur[xa * LD + y];
-            uai[a] = sui[xa * LD + y];
-            const double va = sv[delta * ds + a];
-            vur += va * uar[a];
-            vui += va * uai[a];
-          } else {
-            uar[a] = 0.0;
-            uai[a] = 0.0;
-          }
+        for (int a = 0; a < DS; ++a) {
+          uar[a] = sur[(xr0 + a * S) * LD + y];
+          uai[a] = sui[(xr0 + a * S) * LD + y];
+          const double va = sv[ap * DS + a];
+          vur += va * uar[a];          // (V u)[x][y]
+          vui += va * uai[a];
+          ubr[a] = sur[x * LD + ry0 + a * S];
+          ubi[a] = sui[x * LD + ry0 + a * S];
+          const double vb = sv[a * DS + dc];
+          uvr += ubr[a] * vb;          // (u V)[x][y]
+          uvi += ubi[a] * vb;
         }
-        double zLr = 0.0, zLi = 0.0;
+        double zLr = 0.0, zLi = 0.0, zRr = 0.0, zRi = 0.0;
         int kd = 0;
         for (int q = 0; q < nq; ++q) {
           const double* Zm = Zt + static_cast<long long>(qi[4 * q]) * 2 * dd;
@@ -313,64 +321,14 @@ __global__ __launch_bounds__(GT) void nb_grad_kernel(GradOps g, int s, const dou
           const double cr = qa[2 * q], ci = qa[2 * q + 1];
           zLr += cr * zr_ - ci * zi_;
           zLi += cr * zi_ + ci * zr_;
+          zRr += cr * zr_ + ci * zi_;
+          zRi += cr * zi_ - ci * zr_;
           if (qi[4 * q + 2] > 0) {
 #pragma unroll
             for (int k = 0; k < MAXDOWN; ++k)
               if (k == kd) {
                 pLr[k] += vur * zr_ - vui * zi_;
                 pLi[k] += vur * zi_ + vui * zr_;
-              }
-            ++kd;
-          }
-        }
-#pragma unroll
-        for (int a = 0; a < MAXDS; ++a) TL[a] += uar[a] * zLi + uai[a] * zLr;
-        if (s == 0) {
-          const double* Zn = Zt + static_cast<long long>(n) * 2 * dd;
-          const double zr_ = Zn[x * d + y], zi_ = Zn[x * d + y + dd];
-          double ur_ = 0.0, ui_ = 0.0;
-#pragma unroll
-          for (int a = 0; a < MAXDS; ++a)
-            if (a == delta) {
-              ur_ = uar[a];
-              ui_ = uai[a];
-            }
-          Pr += ur_ * zr_ - ui_ * zi_;
-          Pi += ur_ * zi_ + ui_ * zr_;
-        }
-      }
-      // TR pass: zeta elements with column digit delta
-      for (int e = gi; e < d * R; e += G) {
-        const int x = e / R, r = e - x * R;
-        const int y = digit_row(delta, r, ds, S);
-        double ubr[MAXDS], ubi[MAXDS];
-        double uvr = 0.0, uvi = 0.0;
-#pragma unroll
-        for (int a = 0; a < MAXDS; ++a) {
-          if (a < ds) {
-            const int ya = digit_row(a, r, ds, S);
-            ubr[a] = sur[x * LD + ya];
-            ubi[a] = sui[x * LD + ya];
-            const double va = sv[a * ds + delta];
-            uvr += ubr[a] * va;
-            uvi += ubi[a] * va;
-          } else {
-            ubr[a] = 0.0;
-            ubi[a] = 0.0;
-          }
-        }
-        double zRr = 0.0, zRi = 0.0;
-        int kd = 0;
-        for (int q = 0; q < nq; ++q) {
-          const double* Zm = Zt + static_cast<long long>(qi[4 * q]) * 2 * dd;
-          const double zr_ = Zm[x * d + y], zi_ = Zm[x * d + y + dd];
-          const double cr = qa[2 * q], ci = -qa[2 * q + 1];
-          zRr += cr * zr_ - ci * zi_;
-          zRi += cr * zi_ + ci * zr_;
-          if (qi[4 * q + 2] > 0) {
-#pragma unroll
-            for (int k = 0; k < MAXDOWN; ++k)
-              if (k == kd) {
                 pRr[k] += uvr * zr_ - uvi * zi_;
                 pRi[k] += uvr * zi_ + uvi * zr_;
               }
@@ -378,11 +336,20 @@ __global__ __launch_bounds__(GT) void nb_grad_kernel(GradOps g, int s, const dou
           }
         }
 #pragma unroll
-        for (int a = 0; a < MAXDS; ++a) TR[a] += zRr * ubi[a] + zRi * ubr[a];
+        for (int a = 0; a < DS; ++a) {
+          TL[a] += uar[a] * zLi + uai[a] * zLr;
+          TR[a] += zRr * ubi[a] + zRi * ubr[a];
+        }
+        if (s == 0) {
+          const double* Zn = Zt + static_cast<long long>(n) * 2 * dd;
+          const double zr_ = Zn[x * d + y], zi_ = Zn[x * d + y + dd];
+          const double ur_ = sur[x * LD + y], ui_ = sui[x * LD + y];
+          Pr += ur_ * zr_ - ui_ * zi_;
+          Pi += ur_ * zi_ + ui_ * zr_;
+        }
       }
     }
     // per-item reduction of the lower-neighbour pairings and <u_n, z_n>
-    constexpr int NV = 4 * MAXDOWN + 2;
     double vals[NV];
 #pragma unroll
     for (int k = 0; k < MAXDOWN; ++k) {
@@ -402,15 +369,18 @@ __global__ __launch_bounds__(GT) void nb_grad_kernel(GradOps g, int s, const dou
     if (tid == 0) {
       double tot[NV];
 #pragma unroll
-      for (int k = 0; k < NV; ++k) tot[k] = red[k] + red[NV + k] + red[2 * NV + k] + red[3 * NV + k];
+      for (int k = 0; k < NV; ++k) {
+        tot[k] = 0.0;
+        for (int w = 0; w < NW; ++w) tot[k] += red[w * NV + k];
+      }
       int kd = 0;
       for (int q = 0; q < nq && kd < MAXDOWN; ++q) {
         const int cnt = qi[4 * q + 2];
         if (cnt > 0) {
           const int j = qi[4 * q + 1];
-          const double lr = tot[4 * kd], li = tot[4 * kd + 1], rr = tot[4 * kd + 2], ri = tot[4 * kd + 3];
+          const double lr_ = tot[4 * kd], li = tot[4 * kd + 1], rr = tot[4 * kd + 2], ri = tot[4 * kd + 3];
           atomicAdd(&gc[2 * j], cnt * (li - ri));
-          atomicAdd(&gc[2 * j + 1], cnt * (lr + rr));
+          atomicAdd(&gc[2 * j + 1], cnt * (lr_ + rr));
           ++kd;
         }
       }
@@ -422,20 +392,44 @@ __global__ __launch_bounds__(GT) void nb_grad_kernel(GradOps g, int s, const dou
       }
     }
   }
+  // workgroup reduction: gv[a][ap] += TL[a], gv[dc][a'] -= TR[a']
+  __syncthreads();
+  double* sacc = sur;  // the u planes are free now
+  for (int e = tid; e < DS * DS; e += NBT) sacc[e] = 0.0;
+  __syncthreads();
   if (active) {
 #pragma unroll
-    for (int a = 0; a < MAXDS; ++a) {
-      if (a < ds) {
-        atomicAdd(&gv[a * ds + delta], TL[a]);
-        atomicAdd(&gv[delta * ds + a], -TR[a]);
-      }
+    for (int a = 0; a < DS; ++a) {
+      atomicAdd(&sacc[a * DS + ap], TL[a]);
+      atomicAdd(&sacc[dc * DS + a], -TR[a]);
     }
   }
+  __syncthreads();
+  for (int e = tid; e < DS * DS; e += NBT) atomicAdd(&gv[e], sacc[e]);
 }
 
 size_t nb_grad_lds(int d) {
-  return sizeof(double) * (2 * static_cast<size_t>(d) * (d + 1) + MAXDS * MAXDS + 4 * (4 * MAXDOWN + 2)) +
+  return sizeof(double) * (2 * static_cast<size_t>(d) * (d + 1) + MAXDS * MAXDS + (NBT / 64) * (4 * MAXDOWN + 2)) +
          sizeof(int) * 4 * MAXQ + sizeof(double) * 2 * MAXQ + 64;
+}
+
+template <int DS>
+void nb_grad_ds(const GradOps& g, int s, const double* u, const double* z, long long n_items, double* gv_s,
+                double* gc, double* gnu, hipStream_t stream) {
+  const size_t lds = nb_grad_lds(g.d);
+  static size_t attr = 0;
+  if (lds > attr) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&nb_grad_kernel<DS>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
+      throw std::runtime_error("nb_grad: LDS attribute");
+    attr = lds;
+  }
+  const long long per_cu = std::max<long long>(1, (160 * 1024) / static_cast<long long>(lds));
+  const long long grid = std::min<long long>(n_items, cus() * per_cu);
+  if (grid <= 0) return;
+  hipLaunchKernelGGL((nb_grad_kernel<DS>), dim3(static_cast<unsigned>(grid)), dim3(NBT), lds, stream, g, s, u, z,
+                     n_items, gv_s, gc, gnu);
+  check("nb_grad kernel");
 }
 
 }  // namespace
@@ -445,7 +439,7 @@ int grad_max_parts() { return 1024; }
 bool grad_supported(int d, const int* dims, int n_modes, int max_terms_per_mode) {
   if (d > 80) return false;
   for (int s = 0; s < n_modes; ++s)
-    if (dims[s] > MAXDS) return false;
+    if (dims[s] > MAXDS || dims[s] * d > NBT) return false;
   return 2 * max_terms_per_mode <= MAXQ && max_terms_per_mode <= MAXDOWN;
 }
 
@@ -501,20 +495,17 @@ void launch_reduce_parts(const double* partial, int n_parts, long long len, doub
 
 void launch_nb_grad(const GradOps& g, int s, const double* u, const double* z, long long n_items, double* gv_s,
                     double* gc, double* gnu, hipStream_t stream) {
-  const size_t lds = nb_grad_lds(g.d);
-  static size_t attr = 0;
-  if (lds > attr) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&nb_grad_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
-      throw std::runtime_error("nb_grad: LDS attribute");
-    attr = lds;
+  switch (g.dims[s]) {
+    case 1: nb_grad_ds<1>(g, s, u, z, n_items, gv_s, gc, gnu, stream); break;
+    case 2: nb_grad_ds<2>(g, s, u, z, n_items, gv_s, gc, gnu, stream); break;
+    case 3: nb_grad_ds<3>(g, s, u, z, n_items, gv_s, gc, gnu, stream); break;
+    case 4: nb_grad_ds<4>(g, s, u, z, n_items, gv_s, gc, gnu, stream); break;
+    case 5: nb_grad_ds<5>(g, s, u, z, n_items, gv_s, gc, gnu, stream); break;
+    case 6: nb_grad_ds<6>(g, s, u, z, n_items, gv_s, gc, gnu, stream); break;
+    case 7: nb_grad_ds<7>(g, s, u, z, n_items, gv_s, gc, gnu, stream); break;
+    case 8: nb_grad_ds<8>(g, s, u, z, n_items, gv_s, gc, gnu, stream); break;
+    default: throw std::runtime_error("nb_grad: mode dimension > 8");
   }
-  const long long per_cu = std::max<long long>(1, (160 * 1024) / static_cast<long long>(lds));
-  const long long grid = std::min<long long>(n_items, cus() * per_cu);
-  if (grid <= 0) return;
-  hipLaunchKernelGGL(nb_grad_kernel, dim3(static_cast<unsigned>(grid)), dim3(GT), lds, stream, g, s, u, z, n_items,
-                     gv_s, gc, gnu);
-  check("nb_grad kernel");
 }
 
 }  // namespace heom

@@ -245,8 +245,9 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
     }
 
   // ---- couplings to the hierarchy neighbours ----------------------------
-  // X_s is accumulated row block by row block directly in the LDS planes
-  // (each wave updates only its own rows) from 16-byte loads.
+  // Each wave forms X_s (and Y_s) for its own rows from 16-byte neighbour
+  // loads: in registers, staged once per mode in the LDS planes (FP32), or
+  // accumulated directly in the LDS planes (FP64, whose register form spills).
 #pragma unroll 1
   for (int s = 0; s < 4; ++s) {
     if (s >= sh.nm()) break;
@@ -255,93 +256,178 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
     if (p0 == p1) continue;  // uniform across the workgroup
     const int ds = sh.dim(s), st = sh.stride(s);
     const T* vs = sV + s * 64;
-    // X_s (and W = sum_q Im(aL_q) rho_q, for Y_s) of this wave's rows in
-    // registers, one 16-byte load per vector and neighbour
-    vec_t xr[RV], xi[RV], wr[RV], wi[RV];
-    bool have_w = false;
-#pragma unroll
-    for (int k = 0; k < RV; ++k) {
-#pragma unroll
-      for (int i = 0; i < VW; ++i) {
-        vset<T, VW>(xr[k], i, T(0));
-        vset<T, VW>(xi[k], i, T(0));
-        vset<T, VW>(wr[k], i, T(0));
-        vset<T, VW>(wi[k], i, T(0));
-      }
-    }
-    for (int q = p0; q < p1; ++q) {
-      const T* rm = in + traj_base + static_cast<long long>(op.nb_idx[q]) * 2 * dd + rows0 * d;
-      const T ar = op.nb_a[4 * q], ai = op.nb_a[4 * q + 1];
-      const bool cplx = ai != T(0);
-      have_w = have_w || cplx;
-#pragma unroll
-      for (int k = 0; k < RV; ++k) {
-        const int e = (lane + 64 * k) * VW;
-        if (e < rb_elems) {
-          const vec_t br = *reinterpret_cast<const vec_t*>(rm + e);
-          const vec_t bi = *reinterpret_cast<const vec_t*>(rm + dd + e);
-          xr[k] += ar * br - ai * bi;
-          xi[k] += ar * bi + ai * br;
-          if (cplx) {
-            wr[k] += ai * br;
-            wi[k] += ai * bi;
+    if constexpr (sizeof(T) == 8) {
+      // FP64: the register form below would spill; X_s is accumulated in LDS
+      // and Y_s formed by a second pass over the complex-coefficient neighbours
+    // X_s of this wave's rows accumulated in the LDS planes (each wave
+      // touches only its own rows here), from 16-byte neighbour loads
+      __syncthreads();  // every wave is done with the previous LDS content
+      bool have_w = false;
+      for (int q = p0; q < p1; ++q) {
+        const T* rm = in + traj_base + static_cast<long long>(op.nb_idx[q]) * 2 * dd + rows0 * d;
+        const T ar = op.nb_a[4 * q], ai = op.nb_a[4 * q + 1];
+        have_w = have_w || ai != T(0);
+        const bool first = q == p0;
+  #pragma unroll
+        for (int k = 0; k < RV; ++k) {
+          const int e = (lane + 64 * k) * VW;
+          if (e < rb_elems) {
+            const vec_t br = *reinterpret_cast<const vec_t*>(rm + e);
+            const vec_t bi = *reinterpret_cast<const vec_t*>(rm + dd + e);
+            const int r = rows0 + e / d, c = e - (e / d) * d;
+  #pragma unroll
+            for (int i = 0; i < VW; ++i) {
+              const T xr_ = ar * vget<T, VW>(br, i) - ai * vget<T, VW>(bi, i);
+              const T xi_ = ar * vget<T, VW>(bi, i) + ai * vget<T, VW>(br, i);
+              if (first) {
+                sRe[r * LD + c + i] = xr_;
+                sIm[r * LD + c + i] = xi_;
+              } else {
+                sRe[r * LD + c + i] += xr_;
+                sIm[r * LD + c + i] += xi_;
+              }
+            }
           }
         }
       }
-    }
-    __syncthreads();  // every wave is done with the previous LDS content
-#pragma unroll
-    for (int k = 0; k < RV; ++k) {
-      const int e = (lane + 64 * k) * VW;
-      if (e < rb_elems) {
-        const int r = rows0 + e / d, c = e - (e / d) * d;
-#pragma unroll
-        for (int i = 0; i < VW; ++i) {
-          sRe[r * LD + c + i] = vget<T, VW>(xr[k], i);
-          sIm[r * LD + c + i] = vget<T, VW>(xi[k], i);
-        }
-      }
-    }
-    __syncthreads();
-    // left product: (V_s X_s)[a][c] = sum_k v_s[a_s][k] X_s[a + (k - a_s) st][c];  L += -i V X
-    {
-      int as[4], r0[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int a = rows0 + M::crow(lq, r);
-        as[r] = (a / st) % ds;
-        r0[r] = a - as[r] * st;
-      }
-      for (int k = 0; k < ds; ++k) {
-#pragma unroll
+      __syncthreads();
+      // left product: (V_s X_s)[a][c] = sum_k v_s[a_s][k] X_s[a + (k - a_s) st][c];  L += -i V X
+      {
+        int as[4], r0[4];
+  #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const T v = vs[as[r] * ds + k];
-          const int rowoff = (r0[r] + k * st) * LD + lr;
-#pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            Rre[j][r] += v * sIm[rowoff + 16 * j];
-            Rim[j][r] -= v * sRe[rowoff + 16 * j];
+          const int a = rows0 + M::crow(lq, r);
+          as[r] = (a / st) % ds;
+          r0[r] = a - as[r] * st;
+        }
+        for (int k = 0; k < ds; ++k) {
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const T v = vs[as[r] * ds + k];
+            const int rowoff = (r0[r] + k * st) * LD + lr;
+  #pragma unroll
+            for (int j = 0; j < NB; ++j) {
+              Rre[j][r] += v * sIm[rowoff + 16 * j];
+              Rim[j][r] -= v * sRe[rowoff + 16 * j];
+            }
           }
         }
       }
-    }
-    __syncthreads();  // left products read other waves' rows
-    // Y_s = X_s - 2i W on this wave's rows
-    if (have_w) {
-#pragma unroll
+      // Y_s = X_s - 2i sum_q Im(aL_q) rho_q on this wave's rows: a second pass
+      // over the neighbours with complex coefficients
+      if (have_w) {
+        __syncthreads();  // left products read other waves' rows
+        for (int q = p0; q < p1; ++q) {
+          const T ai = op.nb_a[4 * q + 1];
+          if (ai == T(0)) continue;
+          const T* rm = in + traj_base + static_cast<long long>(op.nb_idx[q]) * 2 * dd + rows0 * d;
+          const T a2 = 2 * ai;
+  #pragma unroll
+          for (int k = 0; k < RV; ++k) {
+            const int e = (lane + 64 * k) * VW;
+            if (e < rb_elems) {
+              const vec_t br = *reinterpret_cast<const vec_t*>(rm + e);
+              const vec_t bi = *reinterpret_cast<const vec_t*>(rm + dd + e);
+              const int r = rows0 + e / d, c = e - (e / d) * d;
+  #pragma unroll
+              for (int i = 0; i < VW; ++i) {
+                sRe[r * LD + c + i] += a2 * vget<T, VW>(bi, i);
+                sIm[r * LD + c + i] -= a2 * vget<T, VW>(br, i);
+              }
+            }
+          }
+        }
+      }
+      __syncthreads();
+    } else {
+    // X_s (and W = sum_q Im(aL_q) rho_q, for Y_s) of this wave's rows in
+      // registers, one 16-byte load per vector and neighbour
+      vec_t xr[RV], xi[RV], wr[RV], wi[RV];
+      bool have_w = false;
+  #pragma unroll
+      for (int k = 0; k < RV; ++k) {
+  #pragma unroll
+        for (int i = 0; i < VW; ++i) {
+          vset<T, VW>(xr[k], i, T(0));
+          vset<T, VW>(xi[k], i, T(0));
+          vset<T, VW>(wr[k], i, T(0));
+          vset<T, VW>(wi[k], i, T(0));
+        }
+      }
+      for (int q = p0; q < p1; ++q) {
+        const T* rm = in + traj_base + static_cast<long long>(op.nb_idx[q]) * 2 * dd + rows0 * d;
+        const T ar = op.nb_a[4 * q], ai = op.nb_a[4 * q + 1];
+        const bool cplx = ai != T(0);
+        have_w = have_w || cplx;
+  #pragma unroll
+        for (int k = 0; k < RV; ++k) {
+          const int e = (lane + 64 * k) * VW;
+          if (e < rb_elems) {
+            const vec_t br = *reinterpret_cast<const vec_t*>(rm + e);
+            const vec_t bi = *reinterpret_cast<const vec_t*>(rm + dd + e);
+            xr[k] += ar * br - ai * bi;
+            xi[k] += ar * bi + ai * br;
+            if (cplx) {
+              wr[k] += ai * br;
+              wi[k] += ai * bi;
+            }
+          }
+        }
+      }
+      __syncthreads();  // every wave is done with the previous LDS content
+  #pragma unroll
       for (int k = 0; k < RV; ++k) {
         const int e = (lane + 64 * k) * VW;
         if (e < rb_elems) {
           const int r = rows0 + e / d, c = e - (e / d) * d;
-#pragma unroll
+  #pragma unroll
           for (int i = 0; i < VW; ++i) {
-            sRe[r * LD + c + i] = vget<T, VW>(xr[k], i) + 2 * vget<T, VW>(wi[k], i);
-            sIm[r * LD + c + i] = vget<T, VW>(xi[k], i) - 2 * vget<T, VW>(wr[k], i);
+            sRe[r * LD + c + i] = vget<T, VW>(xr[k], i);
+            sIm[r * LD + c + i] = vget<T, VW>(xi[k], i);
           }
         }
       }
+      __syncthreads();
+      // left product: (V_s X_s)[a][c] = sum_k v_s[a_s][k] X_s[a + (k - a_s) st][c];  L += -i V X
+      {
+        int as[4], r0[4];
+  #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = rows0 + M::crow(lq, r);
+          as[r] = (a / st) % ds;
+          r0[r] = a - as[r] * st;
+        }
+        for (int k = 0; k < ds; ++k) {
+  #pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const T v = vs[as[r] * ds + k];
+            const int rowoff = (r0[r] + k * st) * LD + lr;
+  #pragma unroll
+            for (int j = 0; j < NB; ++j) {
+              Rre[j][r] += v * sIm[rowoff + 16 * j];
+              Rim[j][r] -= v * sRe[rowoff + 16 * j];
+            }
+          }
+        }
+      }
+      __syncthreads();  // left products read other waves' rows
+      // Y_s = X_s - 2i W on this wave's rows
+      if (have_w) {
+  #pragma unroll
+        for (int k = 0; k < RV; ++k) {
+          const int e = (lane + 64 * k) * VW;
+          if (e < rb_elems) {
+            const int r = rows0 + e / d, c = e - (e / d) * d;
+  #pragma unroll
+            for (int i = 0; i < VW; ++i) {
+              sRe[r * LD + c + i] = vget<T, VW>(xr[k], i) + 2 * vget<T, VW>(wi[k], i);
+              sIm[r * LD + c + i] = vget<T, VW>(xi[k], i) - 2 * vget<T, VW>(wr[k], i);
+            }
+          }
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
     // right product: (Y_s V_s)[a][c] = sum_k Y_s[a][c + (k - c_s) st] v_s[k][c_s];  L += i Y V
     {
       int cs[NB], c0[NB];
