@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 # scaled by the counters' readings for kernels of known size.  Keyed by the
 # kernel source hash: a changed kernel reports traffic null until re-profiled.
 PROFILED_TRAFFIC = {
-    "17692ea95720ccad": {"read_GB": 289.2, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
+    "1138b7a8089565ad": {"read_GB": 286.1, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
 }
 
 PEAKS = {  # MI355X published dense peaks
@@ -130,6 +130,37 @@ def multi_instance(P, torch, precision, stream, compare=False):
     return out
 
 
+def gradient_timing(P, torch, stream):
+    """Reverse-mode gradient (FP64) of a random linear functional of the responses
+    of the three-mode model reduced to depth 3 (220 ADOs), 16 x 16 grid every 10
+    steps, t2 in {0, 65 steps}: seconds for the forward responses and for the
+    vjp (rho held fixed; rho = 200 RK4 steps from the ground state)."""
+    import workloads as w
+    params, _, _ = w.cfg5()
+    params["depth"] = 3
+    grid = {"n1": 16, "n3": 16, "steps_per_sample": 10, "t2_steps": [0, 65]}
+    m = P.heom_model_build(params, stream=stream)
+    rho = P.State(m, 1, "fp64")
+    rho.set_ground()
+    P.heom_propagate(m, rho, 200)
+    P.heom_response_2d(m, rho, {"n1": 2, "n3": 2, "steps_per_sample": 1, "t2_steps": [0]}, "fp64",
+                       "adjoint")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    R = P.heom_response_2d(m, rho, grid, "fp64", "adjoint")
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    W = np.random.default_rng(0).standard_normal(R.shape) + 0j
+    t0 = time.perf_counter()
+    g = P.heom_response_2d_vjp(m, rho, grid, W, stationary=False)
+    torch.cuda.synchronize()
+    t_vjp = time.perf_counter() - t0
+    return {"model": "3-mode, depth 3 (220 ADOs), d = 80", "grid": [16, 16], "t2_steps": [0, 65],
+            "precision": "fp64", "s_forward_responses": t_fwd, "s_vjp": t_vjp,
+            "vjp_over_forward": t_vjp / t_fwd,
+            "finite": bool(np.isfinite(g["H"]).all() and np.isfinite(g["mu"]).all())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +174,7 @@ def main():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--multi", type=int, default=1,
                     help="1: also time the 64-instance uneven batch; 2: and one instance at a time")
+    ap.add_argument("--grad", type=int, default=1, help="also time the reverse-mode gradient")
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "mfma", "mfma_dyn"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -237,6 +269,8 @@ def main():
     if args.multi:
         line["multi_instance"] = multi_instance(P, torch, args.precision, stream.cuda_stream,
                                                 compare=args.multi > 1)
+    if args.grad:
+        line["gradient"] = gradient_timing(P, torch, stream.cuda_stream)
     if args.cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(params)
     print(json.dumps(line))

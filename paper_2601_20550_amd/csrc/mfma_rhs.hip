@@ -1,9 +1,10 @@
 // Fused HEOM right-hand side + RK4 stage on the matrix cores (gfx950 MFMA).
 //
-// A persistent workgroup of NB = ceil(d/16) waves loops over (trajectory,
-// ADO) matrices and computes  out = y + coef * L(in)  for each.  Wave w owns
-// row block w (16 rows) of the zero-padded DP x DP output (DP = 16 NB) and
-// computes every term of those rows:
+// A persistent workgroup of NB = ceil(d/16) row blocks (one or two waves per
+// block) loops over (trajectory, ADO) matrices and computes
+// out = y + coef * L(in)  for each.  Each wave owns a row block (16 rows) of
+// the zero-padded DP x DP output (DP = 16 NB), or half of its column tiles,
+// and computes every term of those outputs:
 //
 //   L rho = -i (H rho - rho H) - gamma_n rho + sum_s [ -i V_s X_s + i Y_s V_s ],
 //   X_s = sum_q aL_q rho_{m_q},   Y_s = sum_q conj(aL_q) rho_{m_q}
@@ -136,13 +137,21 @@ __device__ inline void vset(typename Vec<T, VW>::type& v, int i, T x) {
   }
 }
 
+// Waves per row block: two for the FP32 kernels with 4 <= NB <= 6 (their
+// accumulators and neighbour registers then fit three waves per SIMD, so a
+// 2 NB-wave workgroup spreads evenly over the four SIMDs), one otherwise.
+template <typename T, int NB>
+constexpr int wpr_of() {
+  return (sizeof(T) == 4 && NB >= 4 && NB <= 6) ? 2 : 1;
+}
+
 // Stages H (zero padded to DP x DP), the single-mode operators v_s and zero
 // padding of the rho planes into LDS.
 template <typename T, int NB, typename Shape>
 __device__ inline void stage_operators(const DevOps<T>& op, const Shape& sh, const T* __restrict__ Hp, T* sRe,
                                        T* sH, T* sV) {
   using L = Lds<T, NB>;
-  constexpr int DP = L::DP, LD = L::LD, NT = NB * 64;
+  constexpr int DP = L::DP, LD = L::LD, NT = NB * 64 * wpr_of<T, NB>();
   for (int e = threadIdx.x; e < DP * DP; e += NT) {
     const int r = e / DP, c = e - (e / DP) * DP;
     sH[r * LD + c] = Hp[e];
@@ -159,8 +168,12 @@ __device__ inline void stage_operators(const DevOps<T>& op, const Shape& sh, con
 
 // out = y + coef * L(in) (y may be null: out = L(in)) for matrix `item` of a
 // hierarchy batch whose trajectories start at `in`, `y`, `out`; H and v_s are
-// already in LDS.
-template <typename T, int NB, typename Shape, int VW>
+// already in LDS.  The workgroup has NB * WPR waves: for the matrix-core and
+// contraction work wave w owns row block w / WPR and the column tiles
+// [ (w % WPR) JT, ... ) (JT = ceil(NB / WPR)); for the memory phases
+// (neighbour sums, epilogue) it owns the slab of 16 / WPR rows starting at
+// row (16 / WPR) w.
+template <typename T, int NB, typename Shape, int VW, int WPR>
 __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, const T* __restrict__ in,
                                          const T* y, T* out, T coef, long long item, T* sRe, T* sIm,
                                          const T* sH, const T* sV) {
@@ -169,17 +182,20 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
   using acc_t = typename M::acc;
   using vec_t = typename Vec<T, VW>::type;
   constexpr int DP = L::DP, LD = L::LD;
-  constexpr int NT = NB * 64;
-  // vectors per lane covering a 16-row block of DP columns
-  constexpr int RV = (16 * DP + VW * 64 - 1) / (VW * 64);
+  constexpr int NT = NB * 64 * WPR;
+  constexpr int JT = (NB + WPR - 1) / WPR;   // column tiles per wave
+  constexpr int SR = 16 / WPR;               // slab rows per wave
+  // vectors per lane covering a slab of SR rows of DP columns
+  constexpr int RV = (SR * DP + VW * 64 - 1) / (VW * 64);
   const int d = sh.d();
   const long long dd = static_cast<long long>(d) * d;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int rows0 = 16 * wave;
-  // elements of this wave's row block (rows rows0 .. rows0+15, clipped to d)
-  const int rb_rows = rows0 < d ? (d - rows0 < 16 ? d - rows0 : 16) : 0;
-  const int rb_elems = rb_rows * d;
+  const int rows0 = 16 * (wave / WPR);       // row block (matrix-core phases)
+  const int j0 = (wave % WPR) * JT;          // first column tile
+  const int srow0 = SR * wave;               // slab (memory phases)
+  const int sb_rows = srow0 < d ? (d - srow0 < SR ? d - srow0 : SR) : 0;
+  const int sb_elems = sb_rows * d;
   (void)DP;
   // Per-lane index arithmetic is redone for every item: an opaque copy of
   // the lane id keeps the compiler from hoisting hundreds of LDS addresses
@@ -207,13 +223,13 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
   }
   __syncthreads();
 
-  // ---- H commutator of row block w --------------------------------------
+  // ---- H commutator of row block / column tiles -------------------------
   //   Re L += H Im - Im H,   Im L += Re H - H Re
-  acc_t Rre[NB], Rim[NB];
+  acc_t Rre[JT], Rim[JT];
 #pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    Rre[j] = acc_t{0, 0, 0, 0};
-    Rim[j] = acc_t{0, 0, 0, 0};
+  for (int jj = 0; jj < JT; ++jj) {
+    Rre[jj] = acc_t{0, 0, 0, 0};
+    Rim[jj] = acc_t{0, 0, 0, 0};
   }
 #pragma unroll
   for (int kk = 0; kk < 4 * NB; ++kk) {
@@ -223,12 +239,15 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
     const T aRe = sRe[(rows0 + lr) * LD + k];
     const T naIm = -sIm[(rows0 + lr) * LD + k];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const T hB = sH[k * LD + 16 * j + lr];
-      Rre[j] = M::mma(hA, sIm[k * LD + 16 * j + lr], Rre[j]);
-      Rre[j] = M::mma(naIm, hB, Rre[j]);
-      Rim[j] = M::mma(nhA, sRe[k * LD + 16 * j + lr], Rim[j]);
-      Rim[j] = M::mma(aRe, hB, Rim[j]);
+    for (int jj = 0; jj < JT; ++jj) {
+      if (j0 + jj < NB) {
+        const int j = j0 + jj;
+        const T hB = sH[k * LD + 16 * j + lr];
+        Rre[jj] = M::mma(hA, sIm[k * LD + 16 * j + lr], Rre[jj]);
+        Rre[jj] = M::mma(naIm, hB, Rre[jj]);
+        Rim[jj] = M::mma(nhA, sRe[k * LD + 16 * j + lr], Rim[jj]);
+        Rim[jj] = M::mma(aRe, hB, Rim[jj]);
+      }
     }
     // keep the scheduler from hoisting the LDS operands of many k-slices
     __builtin_amdgcn_sched_barrier(0);
@@ -236,16 +255,18 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
   // damping
   const T g = op.gamma[n];
 #pragma unroll
-  for (int j = 0; j < NB; ++j)
+  for (int jj = 0; jj < JT; ++jj)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int a = rows0 + M::crow(lq, r), c = 16 * j + lr;
-      Rre[j][r] -= g * sRe[a * LD + c];
-      Rim[j][r] -= g * sIm[a * LD + c];
+      const int a = rows0 + M::crow(lq, r), c = 16 * (j0 + jj) + lr;
+      if (j0 + jj < NB) {
+        Rre[jj][r] -= g * sRe[a * LD + c];
+        Rim[jj][r] -= g * sIm[a * LD + c];
+      }
     }
 
   // ---- couplings to the hierarchy neighbours ----------------------------
-  // Each wave forms X_s (and Y_s) for its own rows from 16-byte neighbour
+  // Each wave forms X_s (and Y_s) for its slab rows from 16-byte neighbour
   // loads: in registers, staged once per mode in the LDS planes (FP32), or
   // accumulated directly in the LDS planes (FP64, whose register form spills).
 #pragma unroll 1
@@ -256,26 +277,22 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
     if (p0 == p1) continue;  // uniform across the workgroup
     const int ds = sh.dim(s), st = sh.stride(s);
     const T* vs = sV + s * 64;
+    bool have_w = false;
     if constexpr (sizeof(T) == 8) {
-      // FP64: the register form below would spill; X_s is accumulated in LDS
-      // and Y_s formed by a second pass over the complex-coefficient neighbours
-    // X_s of this wave's rows accumulated in the LDS planes (each wave
-      // touches only its own rows here), from 16-byte neighbour loads
       __syncthreads();  // every wave is done with the previous LDS content
-      bool have_w = false;
       for (int q = p0; q < p1; ++q) {
-        const T* rm = in + traj_base + static_cast<long long>(op.nb_idx[q]) * 2 * dd + rows0 * d;
+        const T* rm = in + traj_base + static_cast<long long>(op.nb_idx[q]) * 2 * dd + srow0 * d;
         const T ar = op.nb_a[4 * q], ai = op.nb_a[4 * q + 1];
         have_w = have_w || ai != T(0);
         const bool first = q == p0;
-  #pragma unroll
+#pragma unroll
         for (int k = 0; k < RV; ++k) {
           const int e = (lane + 64 * k) * VW;
-          if (e < rb_elems) {
+          if (e < sb_elems) {
             const vec_t br = *reinterpret_cast<const vec_t*>(rm + e);
             const vec_t bi = *reinterpret_cast<const vec_t*>(rm + dd + e);
-            const int r = rows0 + e / d, c = e - (e / d) * d;
-  #pragma unroll
+            const int r = srow0 + e / d, c = e - (e / d) * d;
+#pragma unroll
             for (int i = 0; i < VW; ++i) {
               const T xr_ = ar * vget<T, VW>(br, i) - ai * vget<T, VW>(bi, i);
               const T xi_ = ar * vget<T, VW>(bi, i) + ai * vget<T, VW>(br, i);
@@ -291,62 +308,11 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
         }
       }
       __syncthreads();
-      // left product: (V_s X_s)[a][c] = sum_k v_s[a_s][k] X_s[a + (k - a_s) st][c];  L += -i V X
-      {
-        int as[4], r0[4];
-  #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int a = rows0 + M::crow(lq, r);
-          as[r] = (a / st) % ds;
-          r0[r] = a - as[r] * st;
-        }
-        for (int k = 0; k < ds; ++k) {
-  #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const T v = vs[as[r] * ds + k];
-            const int rowoff = (r0[r] + k * st) * LD + lr;
-  #pragma unroll
-            for (int j = 0; j < NB; ++j) {
-              Rre[j][r] += v * sIm[rowoff + 16 * j];
-              Rim[j][r] -= v * sRe[rowoff + 16 * j];
-            }
-          }
-        }
-      }
-      // Y_s = X_s - 2i sum_q Im(aL_q) rho_q on this wave's rows: a second pass
-      // over the neighbours with complex coefficients
-      if (have_w) {
-        __syncthreads();  // left products read other waves' rows
-        for (int q = p0; q < p1; ++q) {
-          const T ai = op.nb_a[4 * q + 1];
-          if (ai == T(0)) continue;
-          const T* rm = in + traj_base + static_cast<long long>(op.nb_idx[q]) * 2 * dd + rows0 * d;
-          const T a2 = 2 * ai;
-  #pragma unroll
-          for (int k = 0; k < RV; ++k) {
-            const int e = (lane + 64 * k) * VW;
-            if (e < rb_elems) {
-              const vec_t br = *reinterpret_cast<const vec_t*>(rm + e);
-              const vec_t bi = *reinterpret_cast<const vec_t*>(rm + dd + e);
-              const int r = rows0 + e / d, c = e - (e / d) * d;
-  #pragma unroll
-              for (int i = 0; i < VW; ++i) {
-                sRe[r * LD + c + i] += a2 * vget<T, VW>(bi, i);
-                sIm[r * LD + c + i] -= a2 * vget<T, VW>(br, i);
-              }
-            }
-          }
-        }
-      }
-      __syncthreads();
     } else {
-    // X_s (and W = sum_q Im(aL_q) rho_q, for Y_s) of this wave's rows in
-      // registers, one 16-byte load per vector and neighbour
       vec_t xr[RV], xi[RV], wr[RV], wi[RV];
-      bool have_w = false;
-  #pragma unroll
+#pragma unroll
       for (int k = 0; k < RV; ++k) {
-  #pragma unroll
+#pragma unroll
         for (int i = 0; i < VW; ++i) {
           vset<T, VW>(xr[k], i, T(0));
           vset<T, VW>(xi[k], i, T(0));
@@ -355,14 +321,14 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
         }
       }
       for (int q = p0; q < p1; ++q) {
-        const T* rm = in + traj_base + static_cast<long long>(op.nb_idx[q]) * 2 * dd + rows0 * d;
+        const T* rm = in + traj_base + static_cast<long long>(op.nb_idx[q]) * 2 * dd + srow0 * d;
         const T ar = op.nb_a[4 * q], ai = op.nb_a[4 * q + 1];
         const bool cplx = ai != T(0);
         have_w = have_w || cplx;
-  #pragma unroll
+#pragma unroll
         for (int k = 0; k < RV; ++k) {
           const int e = (lane + 64 * k) * VW;
-          if (e < rb_elems) {
+          if (e < sb_elems) {
             const vec_t br = *reinterpret_cast<const vec_t*>(rm + e);
             const vec_t bi = *reinterpret_cast<const vec_t*>(rm + dd + e);
             xr[k] += ar * br - ai * bi;
@@ -375,12 +341,12 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
         }
       }
       __syncthreads();  // every wave is done with the previous LDS content
-  #pragma unroll
+#pragma unroll
       for (int k = 0; k < RV; ++k) {
         const int e = (lane + 64 * k) * VW;
-        if (e < rb_elems) {
-          const int r = rows0 + e / d, c = e - (e / d) * d;
-  #pragma unroll
+        if (e < sb_elems) {
+          const int r = srow0 + e / d, c = e - (e / d) * d;
+#pragma unroll
           for (int i = 0; i < VW; ++i) {
             sRe[r * LD + c + i] = vget<T, VW>(xr[k], i);
             sIm[r * LD + c + i] = vget<T, VW>(xi[k], i);
@@ -388,37 +354,38 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
         }
       }
       __syncthreads();
-      // left product: (V_s X_s)[a][c] = sum_k v_s[a_s][k] X_s[a + (k - a_s) st][c];  L += -i V X
+      // left product below; Y_s = X_s - 2i W afterwards from the registers
       {
         int as[4], r0[4];
-  #pragma unroll
+#pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int a = rows0 + M::crow(lq, r);
           as[r] = (a / st) % ds;
           r0[r] = a - as[r] * st;
         }
         for (int k = 0; k < ds; ++k) {
-  #pragma unroll
+#pragma unroll
           for (int r = 0; r < 4; ++r) {
             const T v = vs[as[r] * ds + k];
             const int rowoff = (r0[r] + k * st) * LD + lr;
-  #pragma unroll
-            for (int j = 0; j < NB; ++j) {
-              Rre[j][r] += v * sIm[rowoff + 16 * j];
-              Rim[j][r] -= v * sRe[rowoff + 16 * j];
+#pragma unroll
+            for (int jj = 0; jj < JT; ++jj) {
+              if (j0 + jj < NB) {
+                Rre[jj][r] += v * sIm[rowoff + 16 * (j0 + jj)];
+                Rim[jj][r] -= v * sRe[rowoff + 16 * (j0 + jj)];
+              }
             }
           }
         }
       }
       __syncthreads();  // left products read other waves' rows
-      // Y_s = X_s - 2i W on this wave's rows
       if (have_w) {
-  #pragma unroll
+#pragma unroll
         for (int k = 0; k < RV; ++k) {
           const int e = (lane + 64 * k) * VW;
-          if (e < rb_elems) {
-            const int r = rows0 + e / d, c = e - (e / d) * d;
-  #pragma unroll
+          if (e < sb_elems) {
+            const int r = srow0 + e / d, c = e - (e / d) * d;
+#pragma unroll
             for (int i = 0; i < VW; ++i) {
               sRe[r * LD + c + i] = vget<T, VW>(xr[k], i) + 2 * vget<T, VW>(wi[k], i);
               sIm[r * LD + c + i] = vget<T, VW>(xi[k], i) - 2 * vget<T, VW>(wr[k], i);
@@ -428,25 +395,79 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
       }
       __syncthreads();
     }
+    if constexpr (sizeof(T) == 8) {
+      // left product: (V_s X_s)[a][c] = sum_k v_s[a_s][k] X_s[a + (k - a_s) st][c];  L += -i V X
+      {
+        int as[4], r0[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = rows0 + M::crow(lq, r);
+          as[r] = (a / st) % ds;
+          r0[r] = a - as[r] * st;
+        }
+        for (int k = 0; k < ds; ++k) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const T v = vs[as[r] * ds + k];
+            const int rowoff = (r0[r] + k * st) * LD + lr;
+#pragma unroll
+            for (int jj = 0; jj < JT; ++jj) {
+              if (j0 + jj < NB) {
+                Rre[jj][r] += v * sIm[rowoff + 16 * (j0 + jj)];
+                Rim[jj][r] -= v * sRe[rowoff + 16 * (j0 + jj)];
+              }
+            }
+          }
+        }
+      }
+      // Y_s = X_s - 2i sum_q Im(aL_q) rho_q on the slab rows: a second pass
+      // over the neighbours with complex coefficients
+      if (have_w) {
+        __syncthreads();  // left products read other waves' rows
+        for (int q = p0; q < p1; ++q) {
+          const T ai = op.nb_a[4 * q + 1];
+          if (ai == T(0)) continue;
+          const T* rm = in + traj_base + static_cast<long long>(op.nb_idx[q]) * 2 * dd + srow0 * d;
+          const T a2 = 2 * ai;
+#pragma unroll
+          for (int k = 0; k < RV; ++k) {
+            const int e = (lane + 64 * k) * VW;
+            if (e < sb_elems) {
+              const vec_t br = *reinterpret_cast<const vec_t*>(rm + e);
+              const vec_t bi = *reinterpret_cast<const vec_t*>(rm + dd + e);
+              const int r = srow0 + e / d, c = e - (e / d) * d;
+#pragma unroll
+              for (int i = 0; i < VW; ++i) {
+                sRe[r * LD + c + i] += a2 * vget<T, VW>(bi, i);
+                sIm[r * LD + c + i] -= a2 * vget<T, VW>(br, i);
+              }
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
     // right product: (Y_s V_s)[a][c] = sum_k Y_s[a][c + (k - c_s) st] v_s[k][c_s];  L += i Y V
     {
-      int cs[NB], c0[NB];
+      int cs[JT], c0[JT];
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        const int c = 16 * j + lr;
-        cs[j] = (c / st) % ds;
-        c0[j] = c - cs[j] * st;
+      for (int jj = 0; jj < JT; ++jj) {
+        const int c = 16 * (j0 + jj) + lr;
+        cs[jj] = (c / st) % ds;
+        c0[jj] = c - cs[jj] * st;
       }
       for (int k = 0; k < ds; ++k) {
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          const T v = vs[k * ds + cs[j]];
-          const int coloff = c0[j] + k * st;
+        for (int jj = 0; jj < JT; ++jj) {
+          if (j0 + jj < NB) {
+            const T v = vs[k * ds + cs[jj]];
+            const int coloff = c0[jj] + k * st;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int a = rows0 + M::crow(lq, r);
-            Rre[j][r] -= v * sIm[a * LD + coloff];
-            Rim[j][r] += v * sRe[a * LD + coloff];
+            for (int r = 0; r < 4; ++r) {
+              const int a = rows0 + M::crow(lq, r);
+              Rre[jj][r] -= v * sIm[a * LD + coloff];
+              Rim[jj][r] += v * sRe[a * LD + coloff];
+            }
           }
         }
       }
@@ -454,26 +475,28 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
   }
 
   // ---- epilogue: out = y + coef * L ---------------------------------------
-  // transpose this wave's rows through LDS so that y and out move in
-  // 16-byte vectors
+  // transpose the accumulators through LDS so that y and out move in
+  // 16-byte vectors (slab rows)
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < NB; ++j)
+  for (int jj = 0; jj < JT; ++jj)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int a = rows0 + M::crow(lq, r), c = 16 * j + lr;
-      sRe[a * LD + c] = Rre[j][r];
-      sIm[a * LD + c] = Rim[j][r];
+      const int a = rows0 + M::crow(lq, r), c = 16 * (j0 + jj) + lr;
+      if (j0 + jj < NB) {
+        sRe[a * LD + c] = Rre[jj][r];
+        sIm[a * LD + c] = Rim[jj][r];
+      }
     }
   __syncthreads();
   {
-    const long long ob = base + rows0 * d;
+    const long long ob = base + srow0 * d;
     vec_t yr[RV], yi[RV];
     if (y) {
 #pragma unroll
       for (int k = 0; k < RV; ++k) {
         const int e = (lane + 64 * k) * VW;
-        if (e < rb_elems) {
+        if (e < sb_elems) {
           yr[k] = *reinterpret_cast<const vec_t*>(y + ob + e);
           yi[k] = *reinterpret_cast<const vec_t*>(y + ob + dd + e);
         }
@@ -482,8 +505,8 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
 #pragma unroll
     for (int k = 0; k < RV; ++k) {
       const int e = (lane + 64 * k) * VW;
-      if (e < rb_elems) {
-        const int r = rows0 + e / d, c = e - (e / d) * d;
+      if (e < sb_elems) {
+        const int r = srow0 + e / d, c = e - (e / d) * d;
         vec_t orr, oi;
 #pragma unroll
         for (int i = 0; i < VW; ++i) {
@@ -503,7 +526,7 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
 }
 
 template <typename T, int NB, typename Shape, int MINW, int VW>
-__global__ __launch_bounds__(NB * 64, MINW) void rhs_mfma_kernel(DevOps<T> op, const T* __restrict__ Hp,
+__global__ __launch_bounds__((NB * 64 * wpr_of<T, NB>()), MINW) void rhs_mfma_kernel(DevOps<T> op, const T* __restrict__ Hp,
                                                                  const T* __restrict__ in, const T* y, T* out,
                                                                  T coef, long long n_items) {
   using L = Lds<T, NB>;
@@ -515,7 +538,7 @@ __global__ __launch_bounds__(NB * 64, MINW) void rhs_mfma_kernel(DevOps<T> op, c
   const Shape sh(op.dims, op.strides, op.n_modes, op.d);
   stage_operators<T, NB, Shape>(op, sh, Hp, sRe, sH, sV);
   for (long long item = blockIdx.x; item < n_items; item += gridDim.x)
-    rhs_item<T, NB, Shape, VW>(op, sh, in, y, out, coef, item, sRe, sIm, sH, sV);
+    rhs_item<T, NB, Shape, VW, wpr_of<T, NB>()>(op, sh, in, y, out, coef, item, sRe, sIm, sH, sV);
 }
 
 // Several model instances of one size class (same ceil(d/16)) in one
@@ -523,7 +546,7 @@ __global__ __launch_bounds__(NB * 64, MINW) void rhs_mfma_kernel(DevOps<T> op, c
 // desc[i+1].item_begin).  A workgroup re-stages H and v_s whenever the
 // instance of its next item differs from the previous one.
 template <typename T, int NB, int MINW, int VW>
-__global__ __launch_bounds__(NB * 64, MINW) void rhs_mfma_multi_kernel(const InstDesc<T>* __restrict__ desc,
+__global__ __launch_bounds__((NB * 64 * wpr_of<T, NB>()), MINW) void rhs_mfma_multi_kernel(const InstDesc<T>* __restrict__ desc,
                                                                        int n_inst, T coef, long long n_items) {
   using L = Lds<T, NB>;
   extern __shared__ unsigned char smem_raw[];
@@ -546,7 +569,8 @@ __global__ __launch_bounds__(NB * 64, MINW) void rhs_mfma_multi_kernel(const Ins
       stage_operators<T, NB, DynShape>(di.op, sh, di.Hp, sRe, sH, sV);
       cur = lo;
     }
-    rhs_item<T, NB, DynShape, VW>(di.op, sh, di.in, di.y, di.out, coef, item - di.item_begin, sRe, sIm, sH, sV);
+    rhs_item<T, NB, DynShape, VW, wpr_of<T, NB>()>(di.op, sh, di.in, di.y, di.out, coef, item - di.item_begin, sRe,
+                                                  sIm, sH, sV);
   }
 }
 
@@ -567,7 +591,7 @@ template <typename T, int NB, typename Shape, int VW>
 void launch_shape_vw(const DevOps<T>& op, const T* Hp, const T* in, const T* y, T* out, T coef, long long n_items,
                      int wg_per_cu, hipStream_t stream) {
   const size_t lds = Lds<T, NB>::bytes;
-  constexpr int MINW = (sizeof(T) == 4) ? 2 : 1;
+  constexpr int MINW = (sizeof(T) == 4) ? (wpr_of<T, NB>() == 2 ? 3 : 2) : 1;
   auto kern = &rhs_mfma_kernel<T, NB, Shape, MINW, VW>;
   static bool configured = false;
   if (!configured) {
@@ -575,9 +599,15 @@ void launch_shape_vw(const DevOps<T>& op, const T* Hp, const T* in, const T* y, 
                               static_cast<int>(lds));
     configured = true;
   }
+  int fit = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, reinterpret_cast<const void*>(kern),
+                                                   NB * 64 * wpr_of<T, NB>(), lds) == hipSuccess &&
+      fit > 0 && fit < wg_per_cu)
+    wg_per_cu = fit;
   long long grid = static_cast<long long>(cu_count()) * wg_per_cu;
   if (grid > n_items) grid = n_items;
-  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(NB * 64), lds, stream, op, Hp, in, y, out, coef,
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(NB * 64 * wpr_of<T, NB>()), lds, stream, op, Hp,
+                     in, y, out, coef,
                      n_items);
 }
 
@@ -651,7 +681,7 @@ namespace {
 template <typename T, int NB, int VW>
 void launch_multi_nb(const InstDesc<T>* desc, int n_inst, T coef, long long n_items, hipStream_t stream) {
   const size_t lds = Lds<T, NB>::bytes;
-  constexpr int MINW = (sizeof(T) == 4) ? 2 : 1;
+  constexpr int MINW = (sizeof(T) == 4) ? (wpr_of<T, NB>() == 2 ? 3 : 2) : 1;
   auto kern = &rhs_mfma_multi_kernel<T, NB, MINW, VW>;
   static bool configured = false;
   if (!configured) {
@@ -662,9 +692,15 @@ void launch_multi_nb(const InstDesc<T>* desc, int n_inst, T coef, long long n_it
   int wg = static_cast<int>((160 * 1024) / lds);
   if (wg < 1) wg = 1;
   if (wg > 8) wg = 8;
+  int fit = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, reinterpret_cast<const void*>(kern),
+                                                   NB * 64 * wpr_of<T, NB>(), lds) == hipSuccess &&
+      fit > 0 && fit < wg)
+    wg = fit;
   long long grid = static_cast<long long>(cu_count()) * wg;
   if (grid > n_items) grid = n_items;
-  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(NB * 64), lds, stream, desc, n_inst, coef,
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(NB * 64 * wpr_of<T, NB>()), lds, stream, desc,
+                     n_inst, coef,
                      n_items);
 }
 
