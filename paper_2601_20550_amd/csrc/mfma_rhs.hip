@@ -137,12 +137,12 @@ __device__ inline void vset(typename Vec<T, VW>::type& v, int i, T x) {
   }
 }
 
-// Waves per row block: two for the FP32 kernels with 4 <= NB <= 6 (their
-// accumulators and neighbour registers then fit three waves per SIMD, so a
-// 2 NB-wave workgroup spreads evenly over the four SIMDs), one otherwise.
+// Waves per row block: two for 4 <= NB <= 6 (the accumulators and neighbour
+// registers of a wave then fit three waves per SIMD, so a 2 NB-wave
+// workgroup spreads over the four SIMDs), one otherwise.
 template <typename T, int NB>
 constexpr int wpr_of() {
-  return (sizeof(T) == 4 && NB >= 4 && NB <= 6) ? 2 : 1;
+  return (NB >= 4 && NB <= 6) ? 2 : 1;
 }
 
 // Stages H (zero padded to DP x DP), the single-mode operators v_s and zero
@@ -591,7 +591,7 @@ template <typename T, int NB, typename Shape, int VW>
 void launch_shape_vw(const DevOps<T>& op, const T* Hp, const T* in, const T* y, T* out, T coef, long long n_items,
                      int wg_per_cu, hipStream_t stream) {
   const size_t lds = Lds<T, NB>::bytes;
-  constexpr int MINW = (sizeof(T) == 4) ? (wpr_of<T, NB>() == 2 ? 3 : 2) : 1;
+  constexpr int MINW = (wpr_of<T, NB>() == 2) ? 3 : ((sizeof(T) == 4) ? 2 : 1);
   auto kern = &rhs_mfma_kernel<T, NB, Shape, MINW, VW>;
   static bool configured = false;
   if (!configured) {
@@ -681,7 +681,7 @@ namespace {
 template <typename T, int NB, int VW>
 void launch_multi_nb(const InstDesc<T>* desc, int n_inst, T coef, long long n_items, hipStream_t stream) {
   const size_t lds = Lds<T, NB>::bytes;
-  constexpr int MINW = (sizeof(T) == 4) ? (wpr_of<T, NB>() == 2 ? 3 : 2) : 1;
+  constexpr int MINW = (wpr_of<T, NB>() == 2) ? 3 : ((sizeof(T) == 4) ? 2 : 1);
   auto kern = &rhs_mfma_multi_kernel<T, NB, MINW, VW>;
   static bool configured = false;
   if (!configured) {
