@@ -320,6 +320,14 @@ typedef enum {
 } heom_kernel;
 int heom_model_set_kernel(heom_model* model, int precision, int kernel);
 int heom_model_get_kernel(const heom_model* model, int precision, int* kernel_out);
+/* RK4 propagations of this model of at least `steps` steps replay a HIP graph
+ * of `steps` captured RK4 steps (four stage launches each) instead of
+ * launching every stage (Sec. III fixed-step integration, launch overhead
+ * only).  0 turns graphs off.  Graphs are captured on a private stream per
+ * (buffers, trajectories, generator, precision, kernel) and launched on the
+ * model's stream.  Default 0.  Timing mode (heom_timing_enable) always
+ * launches directly. */
+int heom_model_set_graph_steps(heom_model* model, int steps);
 /* Times every kernel variant on a scratch batch of n_traj trajectories in
  * the given precision (reps RK4 steps each) and keeps the fastest for this
  * model and precision.  ms_out (may be NULL) receives the measured time per

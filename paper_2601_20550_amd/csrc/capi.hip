@@ -142,6 +142,25 @@ struct heom_model {
   // scratch: two hierarchy-sized work buffers per precision, grown on demand
   DevBuf scratch[2];
   DevBuf red_partial, red_result;
+  // captured RK4 step sequences (launch-bound models): graph_steps RK4 steps
+  // per graph, 0 = off; graphs are captured on cap_stream and replayed on stream
+  struct Graph {
+    const void* y;
+    const void* w1;
+    const void* w2;
+    int n_traj;
+    bool adjoint;
+    int prec;
+    int kernel;
+    hipGraphExec_t exec;
+  };
+  int graph_steps = 0;
+  hipStream_t cap_stream = nullptr;
+  std::vector<Graph> graphs;
+  void clear_graphs() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+  }
   // kernel timing
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -149,6 +168,8 @@ struct heom_model {
   long long launches = 0, ado_updates = 0;
 
   ~heom_model() {
+    clear_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (auto& e : events) {
       (void)hipEventDestroy(e.first);
       (void)hipEventDestroy(e.second);
@@ -334,6 +355,7 @@ T* scratch(heom_model* m, int slot, long long elems) {
   size_t bytes = static_cast<size_t>(elems) * sizeof(T);
   if (m->scratch[slot].bytes < bytes) {
     hip_check(hipStreamSynchronize(m->stream), "sync before scratch growth");
+    m->clear_graphs();
     m->scratch[slot] = DevBuf();
     m->scratch[slot] = DevBuf(bytes);
   }
@@ -342,9 +364,63 @@ T* scratch(heom_model* m, int slot, long long elems) {
 
 // n_steps RK4 steps in place on y (n_traj trajectories), with work buffers
 // w1, w2 of the same size:  y <- y + h L(y + h/2 L(y + h/3 L(y + h/4 L y))).
+// One RK4 step as four fused stage launches (Horner form).
+template <typename T>
+void rk4_step_launches(heom_model* m, T* y, T* w1, T* w2, int n_traj, bool adjoint) {
+  const double h = m->hm.dt;
+  launch_stage<T>(m, adjoint, y, y, w1, h / 4.0, n_traj);
+  launch_stage<T>(m, adjoint, w1, y, w2, h / 3.0, n_traj);
+  launch_stage<T>(m, adjoint, w2, y, w1, h / 2.0, n_traj);
+  launch_stage<T>(m, adjoint, w1, y, y, h, n_traj);
+}
+
+// Executable graph of graph_steps RK4 steps on these buffers (captured on
+// first use; null if capture is not possible, which turns graphs off).
+template <typename T>
+hipGraphExec_t rk4_graph(heom_model* m, T* y, T* w1, T* w2, int n_traj, bool adjoint) {
+  for (const auto& g : m->graphs)
+    if (g.y == y && g.w1 == w1 && g.w2 == w2 && g.n_traj == n_traj && g.adjoint == adjoint &&
+        g.prec == prec_of<T>() && g.kernel == m->kernel[prec_of<T>()])
+      return g.exec;
+  if (m->graphs.size() >= 32) m->clear_graphs();
+  if (!m->cap_stream) hip_check(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking), "stream create");
+  hip_check(hipStreamSynchronize(m->stream), "sync");
+  hipStream_t saved = m->stream;
+  m->stream = m->cap_stream;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool ok = hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+  if (ok) {
+    try {
+      for (int s = 0; s < m->graph_steps; ++s) rk4_step_launches<T>(m, y, w1, w2, n_traj, adjoint);
+    } catch (...) {
+      ok = false;
+    }
+    ok = (hipStreamEndCapture(m->cap_stream, &graph) == hipSuccess) && ok && graph;
+  }
+  m->stream = saved;
+  if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipGetLastError();
+  if (!ok) {
+    m->graph_steps = 0;  // fall back to direct launches for this model
+    return nullptr;
+  }
+  m->graphs.push_back({y, w1, w2, n_traj, adjoint, prec_of<T>(), m->kernel[prec_of<T>()], exec});
+  return exec;
+}
+
 template <typename T>
 void rk4_steps(heom_model* m, T* y, T* w1, T* w2, int n_traj, int n_steps, bool adjoint) {
   const double h = m->hm.dt;
+  if (m->graph_steps > 0 && !m->timing && n_steps >= m->graph_steps) {
+    hipGraphExec_t ex = rk4_graph<T>(m, y, w1, w2, n_traj, adjoint);
+    if (ex) {
+      const int reps = n_steps / m->graph_steps;
+      for (int r = 0; r < reps; ++r) hip_check(hipGraphLaunch(ex, m->stream), "graph launch");
+      n_steps -= reps * m->graph_steps;
+    }
+  }
   for (int s = 0; s < n_steps; ++s) {
     stage<T>(m, adjoint, y, y, w1, h / 4.0, n_traj);
     stage<T>(m, adjoint, w1, y, w2, h / 3.0, n_traj);
@@ -1772,6 +1848,17 @@ int heom_model_set_kernel(heom_model* m, int precision, int kernel) {
     if (kernel == HEOM_KERNEL_AUTO) kernel = ok ? HEOM_KERNEL_MFMA : HEOM_KERNEL_GENERIC;
     if (kernel != HEOM_KERNEL_GENERIC && !ok) throw HeomError(HEOM_ERR_PARAM, "matrix-core kernel unsupported for this d");
     m->kernel[precision] = kernel;
+    m->clear_graphs();
+  });
+}
+
+int heom_model_set_graph_steps(heom_model* m, int steps) {
+  return guarded([&] {
+    require_device(m);
+    if (steps < 0) throw HeomError(HEOM_ERR_PARAM, "steps must be >= 0");
+    hip_check(hipStreamSynchronize(m->stream), "sync");
+    m->clear_graphs();
+    m->graph_steps = steps;
   });
 }
 

@@ -127,6 +127,7 @@ _SIGS = {
     "heom_batch_response_2d": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(heom_grid), C.c_int,
                                          C.c_void_p]),
     "heom_model_set_kernel": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    "heom_model_set_graph_steps": (C.c_int, [C.c_void_p, C.c_int]),
     "heom_model_get_kernel": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
     "heom_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int),
                                 C.c_void_p]),
@@ -481,6 +482,41 @@ def heom_params_vjp(params, dirs, grad, step=1e-6):
     return out
 
 
+def response_2d_autograd():
+    """torch.autograd.Function computing R(theta) = heom_response_2d on the
+    stationary state of the model built from params_at(theta), with the
+    reverse-mode gradient (heom_response_2d_vjp, then heom_params_vjp along the
+    parameter directions d params / d theta) as its backward.
+
+    Usage: R = response_2d_autograd().apply(theta, params_at, directions, grid,
+    eq_tol, eq_max_steps); theta is a float64 tensor, R a complex128 tensor
+    [n_t2][2][n1][n3] on the CPU."""
+    import torch
+
+    class _Response2D(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, theta, params_at, directions, grid, eq_tol=1e-12, eq_max_steps=1000000):
+            params = params_at(theta.detach().cpu().numpy())
+            model = heom_model_build(params)
+            rho, _, _ = heom_equilibrate(model, tol=eq_tol, check_every=100, max_steps=eq_max_steps,
+                                         require_convergence=True)
+            R = heom_response_2d(model, rho, grid, "fp64", "adjoint")
+            ctx.model, ctx.rho, ctx.params, ctx.grid = model, rho, params, grid
+            ctx.directions = directions
+            return torch.from_numpy(R)
+
+        @staticmethod
+        def backward(ctx, grad_R):
+            # torch passes dL/dRe R + i dL/dIm R; the library's weights satisfy
+            # dL = Re sum W dR, i.e. W = conj(grad_R)
+            W = np.conj(grad_R.detach().cpu().numpy())
+            g = heom_response_2d_vjp(ctx.model, ctx.rho, ctx.grid, W, stationary=True, tol=1e-12)
+            gt = heom_params_vjp(ctx.params, ctx.directions, g)
+            return torch.from_numpy(gt), None, None, None, None, None
+
+    return _Response2D
+
+
 class Batch:
     """Several models propagated together (one launch per size class and RK4 stage)."""
 
@@ -521,6 +557,10 @@ def heom_batch_response_2d(batch: Batch, rho_eqs, grid, precision="fp32"):
     optr = (C.c_void_p * len(outs))(*[o.ctypes.data for o in outs])
     _check(_lib.heom_batch_response_2d(batch.handle, rho, C.byref(g), _PREC[precision], optr))
     return [(o[0::2] + 1j * o[1::2]).reshape(n_t2, 2, grid["n1"], grid["n3"]) for o in outs]
+
+
+def heom_model_set_graph_steps(model, steps):
+    _check(_lib.heom_model_set_graph_steps(model.handle, int(steps)))
 
 
 def heom_model_set_kernel(model, precision, kernel):

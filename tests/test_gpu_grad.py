@@ -180,3 +180,34 @@ def test_vjp_rejects_unsupported_models():
     with pytest.raises(P.heom2dvs.HeomError) as e:
         P.heom_response_2d_vjp(m, r, grid, _random_W(grid, 1))
     assert e.value.code == P.heom2dvs.HEOM_ERR_PARAM
+
+
+def test_autograd_function_matches_oracle(small):
+    # R(theta) as a torch.autograd.Function (stationary rho from equilibration),
+    # loss Re sum C R, against central differences of the same objective on
+    # the oracle (stationary state by direct solve)
+    import torch
+    params, grid, _, _, _ = small
+    n = w.theta_size(params)
+    rng = np.random.default_rng(13)
+    shape = (len(grid["t2_steps"]), 2, grid["n1"], grid["n3"])
+    Cw = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    F = P.response_2d_autograd()
+    theta = torch.ones(n, dtype=torch.float64, requires_grad=True)
+    R = F.apply(theta, lambda t: w.apply_theta(params, t), w.theta_directions(params), grid)
+    loss = torch.real(torch.sum(torch.from_numpy(Cw) * R))
+    loss.backward()
+
+    def f(t):
+        m = om.build(w.apply_theta(params, t))
+        return og.objective(m, oh.stationary_state(m), grid, Cw)
+
+    ref = np.zeros(n)
+    for i in range(n):
+        tp, tm = np.ones(n), np.ones(n)
+        tp[i] += 1e-5
+        tm[i] -= 1e-5
+        ref[i] = (f(tp) - f(tm)) / 2e-5
+    got = theta.grad.numpy()
+    assert abs(loss.item() - f(np.ones(n))) < 1e-8 * max(1.0, abs(loss.item()))
+    assert np.max(np.abs(got - ref)) < 1e-5 * np.max(np.abs(ref))

@@ -305,3 +305,31 @@ def test_timing_counters():
     ms, n, upd = P.heom_timing_read(m)
     P.heom_timing_enable(m, False)
     assert n == 8 and upd == 8 * 3 * m.n_ado and ms > 0
+
+
+def test_response_2d_three_modes_depth2_parity():
+    # the full pipeline on the three-mode model at depth 2 (55 ADOs, d = 80)
+    m, rho, grid, ref = _response_case("cfg3", 2, 3, 2, [0, 2])
+    got = P.heom_response_2d(m, rho, grid, "fp64", "adjoint")
+    assert _relerr(got, ref) < 1e-10
+    got32 = P.heom_response_2d(m, rho, grid, "fp32", "direct")
+    assert _relerr(got32, ref) < 1e-4
+
+
+def test_full_size_fp32_spectrum_matches_fp64():
+    # full three-mode model (5005 ADOs): the FP32 path against the FP64 path on
+    # a 16 x 16 grid (the oracle cannot run this size); accuracy target of the
+    # FP32 path: 1e-4 of the peak for R and for S_C
+    params = _params("cfg3")
+    m = P.heom_model_build(params)
+    rho = P.State(m, 1, "fp64")
+    rho.set_ground()
+    P.heom_propagate(m, rho, 100)
+    grid = {"n1": 16, "n3": 16, "steps_per_sample": 10, "t2_steps": [0]}
+    r64 = P.heom_response_2d(m, rho, grid, "fp64", "adjoint")
+    r32 = P.heom_response_2d(m, rho, grid, "fp32", "adjoint")
+    assert _relerr(r32, r64) < 1e-4
+    dt_s = 10 * params["dt"]
+    s64 = P.heom_spectrum_2d(r64[0, 0], r64[0, 1], dt_s)
+    s32 = P.heom_spectrum_2d(r32[0, 0], r32[0, 1], dt_s)
+    assert _relerr(s32, s64) < 1e-4
