@@ -199,6 +199,18 @@ int heom_equilibrate(heom_model* model, double tol, int check_every, int min_ste
 
 /* Linear response (Eq. R1): R1(t_k) = i tr{mu G(t_k) mu^x rho_eq},
  * t_k = k * steps_per_sample * dt, k = 0..n-1.  R_out: [n] complex. */
+/* Stationary state by restarted GMRES (Sec. II.C defines rho_eq as the
+ * long-time limit of the propagation from |0><0|; this reaches the same fixed
+ * point, L rho_eq = 0 with tr rho_eq,0 = 1, in fewer steps): after pre_steps
+ * RK4 steps from |0><0|, corrections x solve (I - Phi^m) x = -(I - Phi^m) rho
+ * with m = steps_per_apply RK4 steps per operator application and GMRES
+ * restarted every `restart` applications, until max|L rho| <= tol (the
+ * residual of heom_equilibrate) or max_applies applications.  Outputs as in
+ * heom_equilibrate (applies_out: operator applications); HEOM_ERR_NOCONV (the
+ * state is still returned) if tol is not reached. */
+int heom_equilibrate_krylov(heom_model* model, double tol, int pre_steps, int steps_per_apply, int restart,
+                            int max_applies, heom_state** rho_eq_out, int* applies_out, double* residual_out);
+
 int heom_linear_response(heom_model* model, const heom_state* rho_eq, int n,
                          int steps_per_sample, int precision, double* R_out);
 
@@ -255,9 +267,10 @@ typedef struct {
  * <(L^T)^a lambda, dL L^b y>).  Forward states are recomputed from
  * checkpoints.  rho_is_stationary = 1: rho_eq is the stationary state
  * (L rho_eq = 0, tr rho_eq,0 = 1) and its dependence on the operators is
- * included through the adjoint stationary equation, solved by adjoint
- * propagation until the series term falls below tol x its first term (at most
- * max_steps; stationary_steps / stationary_residual report it;
+ * included through the adjoint stationary equation, solved by restarted
+ * GMRES on (I - (Phi^T)^50) k = h sum_{n<50} (Phi^T)^n r (Phi: the RK4
+ * propagator) until the relative residual is <= tol, using at most max_steps
+ * RK4 steps (stationary_steps / stationary_residual report them;
  * HEOM_ERR_NOCONV if not reached); 0: rho_eq is held fixed.  W: host
  * [n_t2][2][n1][n3] complex.  Needs d <= 80, every mode dimension d_s <= 8
  * with d_s * d <= 512, and K + 1 <= 4 terms per mode (HEOM_ERR_PARAM

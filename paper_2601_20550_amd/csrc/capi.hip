@@ -805,6 +805,135 @@ void batch_response_adjoint(heom_batch* b, const heom_state* const* rho_eq, cons
 namespace {
 
 // ----------------------------------------------------------------------------
+// Stationary problems by GMRES.  With Phi the RK4 propagator of the forward
+// (or transposed) generator, A = I - Phi^m (m RK4 steps) has the stationary
+// state (or the trace functional) as its null vector; on the complement its
+// slow modes are isolated near 0 while every mode that decays within m steps
+// sits near 1, so restarted GMRES converges in far fewer propagation steps
+// than plain time stepping.  FP64, one trajectory.
+struct Krylov {
+  heom_model* m;
+  bool adjoint;
+  int msteps;
+  long long te;
+  DevBuf part, dot, tmp;
+  Krylov(heom_model* mm, bool adj, int ms) : m(mm), adjoint(adj), msteps(ms), te(mm->traj_elems()) {
+    part = DevBuf(static_cast<size_t>(2 * heom::hdot_parts()) * sizeof(double));
+    dot = DevBuf(2 * sizeof(double));
+    tmp = DevBuf(static_cast<size_t>(te) * sizeof(double));
+  }
+  std::complex<double> hdot(const double* x, const double* y) {
+    heom::launch_hdot(x, y, m->hm.n_ado, m->hm.d, part.as<double>(), dot.as<double>(), m->stream);
+    double h[2];
+    hip_check(hipMemcpyAsync(h, dot.p, sizeof(h), hipMemcpyDeviceToHost, m->stream), "copy");
+    hip_check(hipStreamSynchronize(m->stream), "sync");
+    return {h[0], h[1]};
+  }
+  double norm(const double* x) { return std::sqrt(std::max(0.0, hdot(x, x).real())); }
+  void axpy(std::complex<double> a, const double* x, double* y) {
+    heom::launch_axpy(a.real(), a.imag(), x, y, m->hm.n_ado, m->hm.d, m->stream);
+  }
+  void copy(const double* x, double* y) {
+    hip_check(hipMemcpyAsync(y, x, te * sizeof(double), hipMemcpyDeviceToDevice, m->stream), "copy");
+  }
+  void zero(double* y) { hip_check(hipMemsetAsync(y, 0, te * sizeof(double), m->stream), "memset"); }
+  // w = (I - Phi^m) v
+  void apply(const double* v, double* w) {
+    copy(v, tmp.as<double>());
+    rk4_steps_scratch<double>(m, tmp.as<double>(), 1, msteps, adjoint);
+    copy(v, w);
+    axpy(-1.0, tmp.as<double>(), w);
+  }
+};
+
+// Restarted GMRES for (I - Phi^m) x = b from the guess in x.  Stops when the
+// residual estimate is <= rtol ||b|| or after max_applies operator
+// applications; returns the last relative residual estimate.
+double gmres(Krylov& K, const double* b, double* x, int restart, int max_applies, double rtol, int* applies) {
+  using cd = std::complex<double>;
+  const long long te = K.te;
+  DevBuf V(static_cast<size_t>(restart + 1) * te * sizeof(double)), w(static_cast<size_t>(te) * sizeof(double));
+  double* Vp = V.as<double>();
+  const double bnorm = K.norm(b);
+  *applies = 0;
+  if (bnorm == 0.0) {
+    K.zero(x);
+    return 0.0;
+  }
+  double rel = 1.0;
+  while (true) {
+    // r = b - A x into V_0
+    K.apply(x, w.as<double>());
+    ++*applies;
+    K.copy(b, Vp);
+    K.axpy(-1.0, w.as<double>(), Vp);
+    const double beta = K.norm(Vp);
+    rel = beta / bnorm;
+    if (rel <= rtol || *applies >= max_applies) return rel;
+    K.zero(w.as<double>());
+    K.axpy(1.0 / beta, Vp, w.as<double>());
+    K.copy(w.as<double>(), Vp);
+    std::vector<cd> H(static_cast<size_t>(restart + 1) * restart, 0.0), g(restart + 1, 0.0), sn(restart, 0.0);
+    std::vector<double> cs(restart, 0.0);
+    g[0] = beta;
+    int kk = 0;
+    for (int k = 0; k < restart && *applies < max_applies; ++k) {
+      double* vk = Vp + k * te;
+      double* vn = Vp + (k + 1) * te;
+      K.apply(vk, w.as<double>());
+      ++*applies;
+      for (int j = 0; j <= k; ++j) {  // modified Gram-Schmidt
+        const cd h = K.hdot(Vp + j * te, w.as<double>());
+        H[j * restart + k] = h;
+        K.axpy(-h, Vp + j * te, w.as<double>());
+      }
+      const double hn = K.norm(w.as<double>());
+      H[(k + 1) * restart + k] = hn;
+      K.zero(vn);
+      if (hn > 0.0) K.axpy(1.0 / hn, w.as<double>(), vn);
+      for (int j = 0; j < k; ++j) {  // previous rotations
+        const cd a = H[j * restart + k], c = H[(j + 1) * restart + k];
+        H[j * restart + k] = cs[j] * a + sn[j] * c;
+        H[(j + 1) * restart + k] = -std::conj(sn[j]) * a + cs[j] * c;
+      }
+      const cd a = H[k * restart + k];
+      const double bb = std::abs(H[(k + 1) * restart + k]);
+      const double t = std::sqrt(std::norm(a) + bb * bb);
+      if (std::abs(a) == 0.0) {
+        cs[k] = 0.0;
+        sn[k] = 1.0;
+      } else {
+        cs[k] = std::abs(a) / t;
+        sn[k] = (a / std::abs(a)) * std::conj(H[(k + 1) * restart + k]) / t;
+      }
+      H[k * restart + k] = cs[k] * a + sn[k] * H[(k + 1) * restart + k];
+      H[(k + 1) * restart + k] = 0.0;
+      g[k + 1] = -std::conj(sn[k]) * g[k];
+      g[k] = cs[k] * g[k];
+      kk = k + 1;
+      rel = std::abs(g[k + 1]) / bnorm;
+      if (rel <= rtol || hn == 0.0) break;
+    }
+    // x += V y with H y = g (upper triangular)
+    std::vector<cd> y(kk, 0.0);
+    for (int i = kk - 1; i >= 0; --i) {
+      cd acc = g[i];
+      for (int j = i + 1; j < kk; ++j) acc -= H[i * restart + j] * y[j];
+      y[i] = H[i * restart + i] != 0.0 ? acc / H[i * restart + i] : 0.0;
+    }
+    for (int j = 0; j < kk; ++j) K.axpy(y[j], Vp + j * te, x);
+    if (rel <= rtol || *applies >= max_applies) {
+      hip_check(hipStreamSynchronize(K.m->stream), "sync");
+      return rel;
+    }
+  }
+}
+
+}  // namespace
+
+namespace {
+
+// ----------------------------------------------------------------------------
 // Reverse-mode gradient of J = Re sum W R (heom_response_2d_vjp).  FP64.
 //
 // The RK4 propagator is Phi = p(hL), p(z) = 1 + z + z^2/2 + z^3/6 + z^4/24, and
@@ -1103,29 +1232,24 @@ void response_vjp(heom_model* m, const heom_state* rho_eq, const heom_grid& gr, 
     }
     hip_check(hipMemcpyAsync(grho.p, blk.data(), blk.size() * sizeof(double), hipMemcpyHostToDevice, st), "copy");
     hip_check(hipStreamSynchronize(st), "sync");
-    const double r0 = absmax<double>(m, grho.as<double>(), n_ado);
-    DevBuf kd(static_cast<size_t>(te) * sizeof(double));
-    std::vector<double> hc = {g.h, 0.0};
-    DevBuf hcd = upload_coef(hc, st);
-    combine(g, grho.as<double>(), te, 1, kd.as<double>(), te, 1, hcd.as<double>(), 0, 1);
-    double res = r0;
-    int n = 0;
-    const int check_every = 50;
-    while (true) {
-      if (r0 == 0.0 || res <= tol * r0) break;
-      if (n >= max_steps) break;
-      const int k = std::min(check_every, max_steps - n);
-      for (int i = 0; i < k; ++i) {
-        rk4_steps_scratch<double>(m, grho.as<double>(), 1, 1, true);
-        combine(g, grho.as<double>(), te, 1, kd.as<double>(), te, 1, hcd.as<double>(), 1, 1);
+    // kd solves (I - Phi^T) kd = h r; equivalently (I - (Phi^T)^M) kd = h sum_{n<M} (Phi^T)^n r
+    const int M = 50;
+    DevBuf kd(static_cast<size_t>(te) * sizeof(double)), bsum(static_cast<size_t>(te) * sizeof(double));
+    {
+      Krylov K(m, true, M);
+      K.zero(bsum.as<double>());
+      for (int n = 0; n < M; ++n) {
+        if (n) rk4_steps_scratch<double>(m, grho.as<double>(), 1, 1, true);
+        K.axpy(g.h, grho.as<double>(), bsum.as<double>());
       }
-      n += k;
-      res = absmax<double>(m, grho.as<double>(), n_ado);
+      K.zero(kd.as<double>());
+      int applies = 0;
+      const double rel = gmres(K, bsum.as<double>(), kd.as<double>(), 40, std::max(1, max_steps / M), tol, &applies);
+      out->stationary_steps = M + applies * M;
+      out->stationary_residual = rel;
+      if (!(rel <= tol))
+        throw HeomError(HEOM_ERR_NOCONV, "adjoint stationary solve did not converge within max_steps");
     }
-    out->stationary_steps = n;
-    out->stationary_residual = r0 > 0 ? res / r0 : 0.0;
-    if (!(res <= tol * r0) && r0 != 0.0)
-      throw HeomError(HEOM_ERR_NOCONV, "adjoint stationary series did not converge within max_steps");
     DevBuf t1(static_cast<size_t>(te) * sizeof(double)), t2(static_cast<size_t>(te) * sizeof(double));
     stage<double>(m, true, kd.as<double>(), kd.as<double>(), t1.as<double>(), g.h / 4.0, 1);
     stage<double>(m, true, t1.as<double>(), kd.as<double>(), t2.as<double>(), g.h / 3.0, 1);
@@ -1533,6 +1657,53 @@ int heom_equilibrate(heom_model* m, double tol, int check_every, int min_steps, 
   });
   if (rc == HEOM_OK && conv_fail) {
     g_last_error = "equilibration residual above tolerance at max_steps";
+    return HEOM_ERR_NOCONV;
+  }
+  return rc;
+}
+
+int heom_equilibrate_krylov(heom_model* m, double tol, int pre_steps, int steps_per_apply, int restart,
+                            int max_applies, heom_state** rho_eq_out, int* applies_out, double* residual_out) {
+  int conv_fail = 0;
+  int rc = guarded([&] {
+    require_device(m);
+    if (!rho_eq_out) throw HeomError(HEOM_ERR_PARAM, "null output pointer");
+    *rho_eq_out = nullptr;
+    if (pre_steps < 0 || steps_per_apply < 1 || restart < 1 || max_applies < 1 || !(tol > 0.0))
+      throw HeomError(HEOM_ERR_PARAM, "bad Krylov parameters");
+    auto s = new_state(m, 1, HEOM_FP64);
+    heom::launch_set_ground<double>(s->buf.as<double>(), m->traj_elems(), 1, s->n_elems(), m->stream);
+    double* rho = s->buf.as<double>();
+    rk4_steps_scratch<double>(m, rho, 1, pre_steps, false);
+    const long long te = m->traj_elems();
+    Krylov K(m, false, steps_per_apply);
+    DevBuf b(static_cast<size_t>(te) * sizeof(double)), x(static_cast<size_t>(te) * sizeof(double));
+    int used = 0;
+    double res = residual_of<double>(m, rho, 1);
+    if (!std::isfinite(res)) throw HeomError(HEOM_ERR_UNSTABLE, "non-finite hierarchy during equilibration");
+    while (res > tol && used < max_applies) {
+      // rho + x with (I - Phi^m) x = -(I - Phi^m) rho
+      K.apply(rho, b.as<double>());
+      ++used;
+      K.zero(x.as<double>());
+      DevBuf nb(static_cast<size_t>(te) * sizeof(double));
+      K.zero(nb.as<double>());
+      K.axpy(-1.0, b.as<double>(), nb.as<double>());
+      int applies = 0;
+      const double rtol = std::min(1e-2, 0.1 * tol / res);
+      gmres(K, nb.as<double>(), x.as<double>(), restart, max_applies - used, rtol, &applies);
+      used += applies;
+      K.axpy(1.0, x.as<double>(), rho);
+      res = residual_of<double>(m, rho, 1);
+      if (!std::isfinite(res)) throw HeomError(HEOM_ERR_UNSTABLE, "non-finite hierarchy during equilibration");
+    }
+    if (applies_out) *applies_out = used;
+    if (residual_out) *residual_out = res;
+    if (res > tol) conv_fail = 1;
+    *rho_eq_out = s.release();
+  });
+  if (rc == HEOM_OK && conv_fail) {
+    g_last_error = "Krylov equilibration residual above tolerance at max_applies";
     return HEOM_ERR_NOCONV;
   }
   return rc;

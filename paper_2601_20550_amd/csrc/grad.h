@@ -27,6 +27,16 @@ struct GradOps {
 bool grad_supported(int d, const int* dims, int n_modes, int max_terms_per_mode);
 int grad_max_parts();
 
+// out[0] + i out[1] = sum conj(x) y over n_mats complex d x d matrices (FP64);
+// partial must hold 2 hdot_parts() doubles.
+int hdot_parts();
+void launch_hdot(const double* x, const double* y, long long n_mats, int d, double* partial, double* out,
+                 hipStream_t stream);
+
+// y += a x (complex a) over n_mats complex d x d matrices (FP64).
+void launch_axpy(double a_re, double a_im, const double* x, double* y, long long n_mats, int d,
+                 hipStream_t stream);
+
 // out[r] = (accumulate ? out[r] : 0) + sum_s coef[r][s] in[s]; hierarchies of
 // n_mats complex d x d matrices ([mat][re|im][d][d]) at strides in_stride /
 // out_stride doubles; coef_dev: device [n_out][n_in] complex.

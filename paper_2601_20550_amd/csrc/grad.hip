@@ -432,6 +432,63 @@ void nb_grad_ds(const GradOps& g, int s, const double* u, const double* z, long 
   check("nb_grad kernel");
 }
 
+// ---------------------------------------------------------------- hdot -----
+// partial[b] = sum over this block's complex elements of conj(x) y
+__global__ __launch_bounds__(GT) void hdot_kernel(const double* __restrict__ x, const double* __restrict__ y,
+                                                  long long n_c, long long dd, double* __restrict__ partial) {
+  __shared__ double sr[GT / 64], si[GT / 64];
+  double ar = 0.0, ai = 0.0;
+  for (long long c = blockIdx.x * static_cast<long long>(GT) + threadIdx.x; c < n_c;
+       c += static_cast<long long>(gridDim.x) * GT) {
+    const long long mat = c / dd, e = c - mat * dd;
+    const long long off = mat * 2 * dd + e;
+    const double xr = x[off], xi = x[off + dd], yr = y[off], yi = y[off + dd];
+    ar += xr * yr + xi * yi;
+    ai += xr * yi - xi * yr;
+  }
+  ar = wave_sum(ar);
+  ai = wave_sum(ai);
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  if (lane == 0) {
+    sr[wave] = ar;
+    si[wave] = ai;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tr = 0.0, ti = 0.0;
+    for (int w = 0; w < GT / 64; ++w) {
+      tr += sr[w];
+      ti += si[w];
+    }
+    partial[2 * blockIdx.x] = tr;
+    partial[2 * blockIdx.x + 1] = ti;
+  }
+}
+
+__global__ void hdot_final_kernel(const double* __restrict__ partial, int n, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double tr = 0.0, ti = 0.0;
+  for (int b = 0; b < n; ++b) {
+    tr += partial[2 * b];
+    ti += partial[2 * b + 1];
+  }
+  out[0] = tr;
+  out[1] = ti;
+}
+
+// y += a x (complex a) over n_c complex elements
+__global__ __launch_bounds__(GT) void axpy_kernel(double ar, double ai, const double* __restrict__ x,
+                                                  double* __restrict__ y, long long n_c, long long dd) {
+  for (long long c = blockIdx.x * static_cast<long long>(GT) + threadIdx.x; c < n_c;
+       c += static_cast<long long>(gridDim.x) * GT) {
+    const long long mat = c / dd, e = c - mat * dd;
+    const long long off = mat * 2 * dd + e;
+    const double xr = x[off], xi = x[off + dd];
+    y[off] += ar * xr - ai * xi;
+    y[off + dd] += ar * xi + ai * xr;
+  }
+}
+
 }  // namespace
 
 int grad_max_parts() { return 1024; }
@@ -441,6 +498,27 @@ bool grad_supported(int d, const int* dims, int n_modes, int max_terms_per_mode)
   for (int s = 0; s < n_modes; ++s)
     if (dims[s] > MAXDS || dims[s] * d > NBT) return false;
   return 2 * max_terms_per_mode <= MAXQ && max_terms_per_mode <= MAXDOWN;
+}
+
+int hdot_parts() { return 1024; }
+
+void launch_hdot(const double* x, const double* y, long long n_mats, int d, double* partial, double* out,
+                 hipStream_t stream) {
+  const long long dd = static_cast<long long>(d) * d;
+  const long long n_c = n_mats * dd;
+  const int blocks = static_cast<int>(std::max<long long>(1, std::min<long long>((n_c + GT - 1) / GT, hdot_parts())));
+  hipLaunchKernelGGL(hdot_kernel, dim3(blocks), dim3(GT), 0, stream, x, y, n_c, dd, partial);
+  hipLaunchKernelGGL(hdot_final_kernel, dim3(1), dim3(64), 0, stream, partial, blocks, out);
+  check("hdot kernel");
+}
+
+void launch_axpy(double a_re, double a_im, const double* x, double* y, long long n_mats, int d,
+                 hipStream_t stream) {
+  const long long dd = static_cast<long long>(d) * d;
+  const long long n_c = n_mats * dd;
+  const int blocks = static_cast<int>(std::max<long long>(1, std::min<long long>((n_c + GT - 1) / GT, 65536)));
+  hipLaunchKernelGGL(axpy_kernel, dim3(blocks), dim3(GT), 0, stream, a_re, a_im, x, y, n_c, dd);
+  check("axpy kernel");
 }
 
 void launch_combine(const double* in, long long in_stride, int n_in, double* out, long long out_stride, int n_out,

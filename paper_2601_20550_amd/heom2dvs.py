@@ -110,6 +110,9 @@ _SIGS = {
     "heom_equilibrate": (C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int,
                                    C.POINTER(C.c_void_p), C.POINTER(C.c_int),
                                    C.POINTER(C.c_double)]),
+    "heom_equilibrate_krylov": (C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int,
+                                          C.POINTER(C.c_void_p), C.POINTER(C.c_int),
+                                          C.POINTER(C.c_double)]),
     "heom_linear_response": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int,
                                        C.c_void_p]),
     "heom_response_2d": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(heom_grid), C.c_int,
@@ -384,6 +387,20 @@ def heom_equilibrate(model, tol=1e-10, check_every=100, min_steps=0, max_steps=1
     return State(model, handle=h), steps.value, res.value
 
 
+def heom_equilibrate_krylov(model, tol=1e-10, pre_steps=100, steps_per_apply=50, restart=40,
+                            max_applies=2000):
+    """Stationary state by GMRES on (I - Phi^m); returns (state, applications, residual)."""
+    h = C.c_void_p()
+    applies, res = C.c_int(), C.c_double()
+    rc = _lib.heom_equilibrate_krylov(model.handle, float(tol), int(pre_steps), int(steps_per_apply),
+                                      int(restart), int(max_applies), C.byref(h), C.byref(applies),
+                                      C.byref(res))
+    if rc == HEOM_ERR_NOCONV and h.value:
+        _lib.heom_state_free(h)
+    _check(rc)
+    return State(model, handle=h), applies.value, res.value
+
+
 def heom_linear_response(model, rho_eq: State, n: int, steps_per_sample: int, precision="fp64"):
     out = np.zeros(2 * n)
     _check(_lib.heom_linear_response(model.handle, rho_eq.handle, int(n), int(steps_per_sample),
@@ -498,8 +515,7 @@ def response_2d_autograd():
         def forward(ctx, theta, params_at, directions, grid, eq_tol=1e-12, eq_max_steps=1000000):
             params = params_at(theta.detach().cpu().numpy())
             model = heom_model_build(params)
-            rho, _, _ = heom_equilibrate(model, tol=eq_tol, check_every=100, max_steps=eq_max_steps,
-                                         require_convergence=True)
+            rho, _, _ = heom_equilibrate_krylov(model, tol=eq_tol, max_applies=max(1, eq_max_steps // 50))
             R = heom_response_2d(model, rho, grid, "fp64", "adjoint")
             ctx.model, ctx.rho, ctx.params, ctx.grid = model, rho, params, grid
             ctx.directions = directions
@@ -510,7 +526,7 @@ def response_2d_autograd():
             # torch passes dL/dRe R + i dL/dIm R; the library's weights satisfy
             # dL = Re sum W dR, i.e. W = conj(grad_R)
             W = np.conj(grad_R.detach().cpu().numpy())
-            g = heom_response_2d_vjp(ctx.model, ctx.rho, ctx.grid, W, stationary=True, tol=1e-12)
+            g = heom_response_2d_vjp(ctx.model, ctx.rho, ctx.grid, W, stationary=True, tol=1e-11)
             gt = heom_params_vjp(ctx.params, ctx.directions, g)
             return torch.from_numpy(gt), None, None, None, None, None
 

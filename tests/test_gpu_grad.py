@@ -69,11 +69,11 @@ def test_vjp_operator_gradients(small, stationary):
     m = P.heom_model_build(params)
     r = P.State(m, 1, "fp64")
     r.upload(rho[None])
-    got = P.heom_response_2d_vjp(m, r, grid, W, stationary=stationary, tol=1e-13)
+    got = P.heom_response_2d_vjp(m, r, grid, W, stationary=stationary, tol=1e-11)
     ref = og.operator_gradient_fd(o, rho, grid, W, stationary=stationary)
     _compare(got, ref, 1e-6)
     if stationary:
-        assert got["stationary_steps"] > 0 and got["stationary_residual"] <= 1e-13
+        assert got["stationary_steps"] > 0 and got["stationary_residual"] <= 1e-11
 
 
 def test_vjp_single_t2_and_single_sample_edges(small):
@@ -103,7 +103,7 @@ def test_parameter_gradient_end_to_end(small):
     for q in range(R.shape[0]):
         S = P.heom_spectrum_2d(R[q, 0], R[q, 1], dt_s)
         W[q] = P.heom_spectrum_2d_vjp(2.0 * (S - S_t[q]), grid["n1"], grid["n3"], dt_s)
-    g = P.heom_response_2d_vjp(m, r, grid, W, stationary=True, tol=1e-13)
+    g = P.heom_response_2d_vjp(m, r, grid, W, stationary=True, tol=1e-11)
     got = P.heom_params_vjp(params, w.theta_directions(params), g)
     assert np.max(np.abs(got - ref)) < 1e-5 * np.max(np.abs(ref))
 

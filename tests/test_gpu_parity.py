@@ -333,3 +333,32 @@ def test_full_size_fp32_spectrum_matches_fp64():
     s64 = P.heom_spectrum_2d(r64[0, 0], r64[0, 1], dt_s)
     s32 = P.heom_spectrum_2d(r32[0, 0], r32[0, 1], dt_s)
     assert _relerr(s32, s64) < 1e-4
+
+
+@pytest.mark.parametrize("which,depth", [("cfg1", None), ("cfg2", 2)])
+def test_krylov_equilibration_reaches_stationary_state(which, depth):
+    params = _params(which, depth)
+    if which == "cfg1":
+        params["dt"] = 0.05
+    o = om.build(params)
+    ref = oh.stationary_state(o)
+    m = P.heom_model_build(params)
+    rho, applies, res = P.heom_equilibrate_krylov(m, tol=1e-11)
+    assert res <= 1e-11 and applies > 0
+    got = rho.download()[0]
+    assert np.max(np.abs(got - ref)) < 1e-8 * np.max(np.abs(ref))
+
+
+def test_krylov_equilibration_three_modes_is_stationary():
+    # d = 80 at depth 1 (the oracle's sparse direct solve is too slow at this
+    # size): the state must be stationary under the oracle's generator, have
+    # unit trace and a Hermitian system part
+    params = _params("cfg3", 1)
+    o = om.build(params)
+    m = P.heom_model_build(params)
+    rho, applies, res = P.heom_equilibrate_krylov(m, tol=1e-11)
+    got = rho.download()[0]
+    assert res <= 1e-11
+    assert np.max(np.abs(oh.rhs(o, got))) < 1e-10
+    assert abs(np.trace(got[0]) - 1.0) < 1e-12
+    assert np.max(np.abs(got[0] - got[0].conj().T)) < 1e-10
