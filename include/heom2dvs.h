@@ -210,6 +210,11 @@ int heom_equilibrate(heom_model* model, double tol, int check_every, int min_ste
  * state is still returned) if tol is not reached. */
 int heom_equilibrate_krylov(heom_model* model, double tol, int pre_steps, int steps_per_apply, int restart,
                             int max_applies, heom_state** rho_eq_out, int* applies_out, double* residual_out);
+/* The same GMRES corrections applied in place to an existing FP64
+ * one-trajectory state with unit trace (e.g. to continue a previous call in
+ * chunks).  HEOM_ERR_NOCONV (state updated) if tol is not reached. */
+int heom_stationary_refine(heom_model* model, heom_state* rho, double tol, int steps_per_apply, int restart,
+                           int max_applies, int* applies_out, double* residual_out);
 
 int heom_linear_response(heom_model* model, const heom_state* rho_eq, int n,
                          int steps_per_sample, int precision, double* R_out);
@@ -268,7 +273,7 @@ typedef struct {
  * checkpoints.  rho_is_stationary = 1: rho_eq is the stationary state
  * (L rho_eq = 0, tr rho_eq,0 = 1) and its dependence on the operators is
  * included through the adjoint stationary equation, solved by restarted
- * GMRES on (I - (Phi^T)^50) k = h sum_{n<50} (Phi^T)^n r (Phi: the RK4
+ * GMRES on (I - (Phi^T)^500) k = h sum_{n<500} (Phi^T)^n r (Phi: the RK4
  * propagator) until the relative residual is <= tol, using at most max_steps
  * RK4 steps (stationary_steps / stationary_residual report them;
  * HEOM_ERR_NOCONV if not reached); 0: rho_eq is held fixed.  W: host

@@ -1032,9 +1032,7 @@ void sweep(GradCtx& g, const double* S0, double* O, int nt, int n, bool stored_a
   hipStream_t st = m->stream;
   const long long N = static_cast<long long>(nt) * g.te;
   ensure(g.S, g.cap_S, static_cast<long long>(n) * 4 * N, st);
-  long long capO = std::max(g.cap_O, 0LL);
   ensure(g.Ob, g.cap_O, 8 * N, st);
-  (void)capO;
   double* S = g.S.as<double>();
   double* Ob = g.Ob.as<double>();       // Ob[0..3]: on-the-fly powers
   double* Zp = Ob + 4 * N;              // combined partners z'_a
@@ -1233,7 +1231,7 @@ void response_vjp(heom_model* m, const heom_state* rho_eq, const heom_grid& gr, 
     hip_check(hipMemcpyAsync(grho.p, blk.data(), blk.size() * sizeof(double), hipMemcpyHostToDevice, st), "copy");
     hip_check(hipStreamSynchronize(st), "sync");
     // kd solves (I - Phi^T) kd = h r; equivalently (I - (Phi^T)^M) kd = h sum_{n<M} (Phi^T)^n r
-    const int M = 50;
+    const int M = 500;
     DevBuf kd(static_cast<size_t>(te) * sizeof(double)), bsum(static_cast<size_t>(te) * sizeof(double));
     {
       Krylov K(m, true, M);
@@ -1244,7 +1242,7 @@ void response_vjp(heom_model* m, const heom_state* rho_eq, const heom_grid& gr, 
       }
       K.zero(kd.as<double>());
       int applies = 0;
-      const double rel = gmres(K, bsum.as<double>(), kd.as<double>(), 40, std::max(1, max_steps / M), tol, &applies);
+      const double rel = gmres(K, bsum.as<double>(), kd.as<double>(), 100, std::max(1, max_steps / M), tol, &applies);
       out->stationary_steps = M + applies * M;
       out->stationary_residual = rel;
       if (!(rel <= tol))
@@ -1662,6 +1660,39 @@ int heom_equilibrate(heom_model* m, double tol, int check_every, int min_steps, 
   return rc;
 }
 
+namespace {
+
+// GMRES corrections of rho (one FP64 trajectory, unit trace) until
+// max|L rho| <= tol or max_applies operator applications.
+void krylov_refine(heom_model* m, double* rho, double tol, int steps_per_apply, int restart, int max_applies,
+                   int* used_out, double* res_out) {
+  const long long te = m->traj_elems();
+  Krylov K(m, false, steps_per_apply);
+  DevBuf b(static_cast<size_t>(te) * sizeof(double)), x(static_cast<size_t>(te) * sizeof(double));
+  int used = 0;
+  double res = residual_of<double>(m, rho, 1);
+  if (!std::isfinite(res)) throw HeomError(HEOM_ERR_UNSTABLE, "non-finite hierarchy during equilibration");
+  while (res > tol && used < max_applies) {
+    // rho + x with (I - Phi^m) x = -(I - Phi^m) rho
+    K.apply(rho, x.as<double>());
+    ++used;
+    K.zero(b.as<double>());
+    K.axpy(-1.0, x.as<double>(), b.as<double>());
+    K.zero(x.as<double>());
+    int applies = 0;
+    const double rtol = std::min(1e-2, 0.1 * tol / res);
+    gmres(K, b.as<double>(), x.as<double>(), restart, std::max(1, max_applies - used), rtol, &applies);
+    used += applies;
+    K.axpy(1.0, x.as<double>(), rho);
+    res = residual_of<double>(m, rho, 1);
+    if (!std::isfinite(res)) throw HeomError(HEOM_ERR_UNSTABLE, "non-finite hierarchy during equilibration");
+  }
+  *used_out = used;
+  *res_out = res;
+}
+
+}  // namespace
+
 int heom_equilibrate_krylov(heom_model* m, double tol, int pre_steps, int steps_per_apply, int restart,
                             int max_applies, heom_state** rho_eq_out, int* applies_out, double* residual_out) {
   int conv_fail = 0;
@@ -1673,30 +1704,10 @@ int heom_equilibrate_krylov(heom_model* m, double tol, int pre_steps, int steps_
       throw HeomError(HEOM_ERR_PARAM, "bad Krylov parameters");
     auto s = new_state(m, 1, HEOM_FP64);
     heom::launch_set_ground<double>(s->buf.as<double>(), m->traj_elems(), 1, s->n_elems(), m->stream);
-    double* rho = s->buf.as<double>();
-    rk4_steps_scratch<double>(m, rho, 1, pre_steps, false);
-    const long long te = m->traj_elems();
-    Krylov K(m, false, steps_per_apply);
-    DevBuf b(static_cast<size_t>(te) * sizeof(double)), x(static_cast<size_t>(te) * sizeof(double));
+    rk4_steps_scratch<double>(m, s->buf.as<double>(), 1, pre_steps, false);
     int used = 0;
-    double res = residual_of<double>(m, rho, 1);
-    if (!std::isfinite(res)) throw HeomError(HEOM_ERR_UNSTABLE, "non-finite hierarchy during equilibration");
-    while (res > tol && used < max_applies) {
-      // rho + x with (I - Phi^m) x = -(I - Phi^m) rho
-      K.apply(rho, b.as<double>());
-      ++used;
-      K.zero(x.as<double>());
-      DevBuf nb(static_cast<size_t>(te) * sizeof(double));
-      K.zero(nb.as<double>());
-      K.axpy(-1.0, b.as<double>(), nb.as<double>());
-      int applies = 0;
-      const double rtol = std::min(1e-2, 0.1 * tol / res);
-      gmres(K, nb.as<double>(), x.as<double>(), restart, max_applies - used, rtol, &applies);
-      used += applies;
-      K.axpy(1.0, x.as<double>(), rho);
-      res = residual_of<double>(m, rho, 1);
-      if (!std::isfinite(res)) throw HeomError(HEOM_ERR_UNSTABLE, "non-finite hierarchy during equilibration");
-    }
+    double res = 0.0;
+    krylov_refine(m, s->buf.as<double>(), tol, steps_per_apply, restart, max_applies, &used, &res);
     if (applies_out) *applies_out = used;
     if (residual_out) *residual_out = res;
     if (res > tol) conv_fail = 1;
@@ -1704,6 +1715,30 @@ int heom_equilibrate_krylov(heom_model* m, double tol, int pre_steps, int steps_
   });
   if (rc == HEOM_OK && conv_fail) {
     g_last_error = "Krylov equilibration residual above tolerance at max_applies";
+    return HEOM_ERR_NOCONV;
+  }
+  return rc;
+}
+
+int heom_stationary_refine(heom_model* m, heom_state* rho, double tol, int steps_per_apply, int restart,
+                           int max_applies, int* applies_out, double* residual_out) {
+  int conv_fail = 0;
+  int rc = guarded([&] {
+    require_device(m);
+    require_state(m, rho);
+    if (rho->precision != HEOM_FP64 || rho->n_traj != 1)
+      throw HeomError(HEOM_ERR_STATE, "rho must be an FP64 state with one trajectory");
+    if (steps_per_apply < 1 || restart < 1 || max_applies < 1 || !(tol > 0.0))
+      throw HeomError(HEOM_ERR_PARAM, "bad Krylov parameters");
+    int used = 0;
+    double res = 0.0;
+    krylov_refine(m, rho->buf.as<double>(), tol, steps_per_apply, restart, max_applies, &used, &res);
+    if (applies_out) *applies_out = used;
+    if (residual_out) *residual_out = res;
+    if (res > tol) conv_fail = 1;
+  });
+  if (rc == HEOM_OK && conv_fail) {
+    g_last_error = "stationary residual above tolerance at max_applies";
     return HEOM_ERR_NOCONV;
   }
   return rc;

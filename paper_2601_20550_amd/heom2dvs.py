@@ -113,6 +113,8 @@ _SIGS = {
     "heom_equilibrate_krylov": (C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int,
                                           C.POINTER(C.c_void_p), C.POINTER(C.c_int),
                                           C.POINTER(C.c_double)]),
+    "heom_stationary_refine": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.c_int, C.c_int,
+                                         C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "heom_linear_response": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int,
                                        C.c_void_p]),
     "heom_response_2d": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(heom_grid), C.c_int,
@@ -387,8 +389,8 @@ def heom_equilibrate(model, tol=1e-10, check_every=100, min_steps=0, max_steps=1
     return State(model, handle=h), steps.value, res.value
 
 
-def heom_equilibrate_krylov(model, tol=1e-10, pre_steps=100, steps_per_apply=50, restart=40,
-                            max_applies=2000):
+def heom_equilibrate_krylov(model, tol=1e-10, pre_steps=100, steps_per_apply=500, restart=100,
+                            max_applies=400):
     """Stationary state by GMRES on (I - Phi^m); returns (state, applications, residual)."""
     h = C.c_void_p()
     applies, res = C.c_int(), C.c_double()
@@ -399,6 +401,17 @@ def heom_equilibrate_krylov(model, tol=1e-10, pre_steps=100, steps_per_apply=50,
         _lib.heom_state_free(h)
     _check(rc)
     return State(model, handle=h), applies.value, res.value
+
+
+def heom_stationary_refine(model, state, tol=1e-10, steps_per_apply=500, restart=100, max_applies=100,
+                           require_convergence=False):
+    """GMRES corrections of `state` in place; returns (applications, residual)."""
+    applies, res = C.c_int(), C.c_double()
+    rc = _lib.heom_stationary_refine(model.handle, state.handle, float(tol), int(steps_per_apply),
+                                     int(restart), int(max_applies), C.byref(applies), C.byref(res))
+    if rc != HEOM_ERR_NOCONV or require_convergence:
+        _check(rc)
+    return applies.value, res.value
 
 
 def heom_linear_response(model, rho_eq: State, n: int, steps_per_sample: int, precision="fp64"):
@@ -515,7 +528,7 @@ def response_2d_autograd():
         def forward(ctx, theta, params_at, directions, grid, eq_tol=1e-12, eq_max_steps=1000000):
             params = params_at(theta.detach().cpu().numpy())
             model = heom_model_build(params)
-            rho, _, _ = heom_equilibrate_krylov(model, tol=eq_tol, max_applies=max(1, eq_max_steps // 50))
+            rho, _, _ = heom_equilibrate_krylov(model, tol=eq_tol, max_applies=max(1, eq_max_steps // 500))
             R = heom_response_2d(model, rho, grid, "fp64", "adjoint")
             ctx.model, ctx.rho, ctx.params, ctx.grid = model, rho, params, grid
             ctx.directions = directions
