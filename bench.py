@@ -176,6 +176,9 @@ def main():
     ap.add_argument("--multi", type=int, default=1,
                     help="1: also time the 64-instance uneven batch; 2: and one instance at a time")
     ap.add_argument("--grad", type=int, default=1, help="also time the reverse-mode gradient")
+    ap.add_argument("--workload", default="cfg3", choices=["cfg3", "paper"],
+                    help="cfg3: 3-mode, 80 states, depth 6 (5005 ADOs); paper: the paper's hierarchy "
+                         "scale, 3 x 4 levels, K = 4 Pade, depth 5 (15,504 ADOs), 300 K assumed")
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "mfma", "mfma_dyn"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -188,7 +191,10 @@ def main():
     import workloads as w
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    params, grid = w.cfg3(depth=args.depth)
+    if args.workload == "paper":
+        params, grid = w.paper_scale()
+    else:
+        params, grid = w.cfg3(depth=args.depth)
     stream = torch.cuda.current_stream()
     m = P.heom_model_build(params, stream=stream.cuda_stream)
     B = args.batch
@@ -233,8 +239,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic (seeded water-like 3-mode model; no trained inputs)",
-        "config": {"workload": f"3-mode MAB HEOM, 80 states, K=2 Pade x3, depth {args.depth} "
-                               f"({m.n_ado} ADOs), {B} trajectories batched, RK4 dt=0.1",
+        "config": {"workload": (f"3-mode MAB HEOM, 80 states, K=2 Pade x3, depth {args.depth} "
+                                if args.workload == "cfg3" else
+                                f"3-mode MAB HEOM at the paper's scale, 64 states, K=4 Pade x3, depth "
+                                f"{params['depth']}, 300 K assumed ")
+                               + f"({m.n_ado} ADOs), {B} trajectories batched, RK4 dt=0.1",
                    "n_ado": m.n_ado, "d": m.d, "trajectories": B},
         "roofline": {"bound": "alu" if kernel == "generic" else "mfma", "achieved": achieved,
                      "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
@@ -248,7 +257,7 @@ def main():
 
     prof = PROFILED_TRAFFIC.get(kernel_source_hash())
     if (prof and kernel.startswith("mfma") and prof["batch"] == B
-            and prof["precision"] == args.precision and args.depth == 6):
+            and prof["precision"] == args.precision and args.depth == 6 and args.workload == "cfg3"):
         line["roofline"]["traffic"] = (prof["read_GB"] + prof["write_GB"]) * 1e9
         line["roofline"]["traffic_unit"] = "bytes per launch (HBM, calibrated rocprofv3 counters)"
         line["roofline"]["hbm_GBs_at_traffic"] = line["roofline"]["traffic"] / avg_launch_s / 1e9

@@ -231,6 +231,19 @@ int heom_linear_response(heom_model* model, const heom_state* rho_eq, int n,
 int heom_response_2d(heom_model* model, const heom_state* rho_eq, const heom_grid* grid,
                      int precision, int method, int max_batch, double* R_out);
 
+/* Third-order responses of arbitrary dipole pathways (the full 8-term
+ * response of Eq. RFTIRI with D1 = D2 = D3 = mu, double-quantum and other
+ * phase-matched pathways): pathway p applies (D1, D2, D3) = (ops[3p],
+ * ops[3p+1], ops[3p+2]), each a heom_operator, i.e.
+ * R_p = i^3 tr{mu G(t3) D3^x G(t2) D2^x G(t1) D1^x rho_eq} on the grid, with
+ * the same methods, precisions and batching as heom_response_2d (which is
+ * this call with the pathways I = (mu-, mu+, mu+) and II = (mu+, mu-, mu+)).
+ * R_out: host [n_t2][n_pathways][n1][n3] complex.  HEOM_ERR_PARAM for an
+ * operator outside heom_operator or n_pathways < 1. */
+int heom_response_2d_pathways(heom_model* model, const heom_state* rho_eq, const heom_grid* grid,
+                              int precision, int method, int max_batch, int n_pathways, const int* ops,
+                              double* R_out);
+
 /* 2D correlation spectrum (Eq. correlation-spectrum) from the two pathway
  * responses, computed on the device in FP64: trapezoid weights (1/2 at t=0),
  * zero padding to 2n, Omega_m = 2 pi m/(2 n dt_s), m = -n..n-1,
@@ -240,6 +253,13 @@ int heom_response_2d(heom_model* model, const heom_state* rho_eq, const heom_gri
  * [2 n3][2 n1] doubles (rows W3, columns W1). */
 int heom_spectrum_2d(const double* R_I, const double* R_II, int n1, int n3, double dt_s,
                      double* S_out);
+
+/* Linear absorption line shape from R1 (heom_linear_response): the same
+ * trapezoid-weighted DFT as heom_spectrum_2d in one dimension,
+ * I(W_m) = sum_k w_k dt_s exp(i W_m t_k) R1(t_k), W_m = 2 pi m/(2 n dt_s),
+ * m = -n..n-1 (Sec. II.C, linear response).  R1: [n] complex; I_out: [2n]
+ * complex host arrays.  Host computation, FP64. */
+int heom_spectrum_1d(const double* R1, int n, double dt_s, double* I_out);
 
 /* ------------------------------------------------------- gradients ----- */
 /* Gradients of a real objective J = Re sum W[q][P][j][k] R[q][P][j][k] of the

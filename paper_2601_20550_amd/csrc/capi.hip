@@ -555,8 +555,11 @@ int auto_batch(heom_model* m, int n_total, size_t elem, long long per_traj_buffe
   return static_cast<int>(std::min<long long>(c, n_total));
 }
 
+// Pathway p applies (D1, D2, D3) = (ops[3p], ops[3p+1], ops[3p+2]) (heom_operator
+// values); R is written as [n_t2][n_pw][n1][n3] complex.
 template <typename T>
-void response_direct(heom_model* m, const heom_state* rho_eq, const heom_grid& g, int max_batch, double* Rdev) {
+void response_direct(heom_model* m, const heom_state* rho_eq, const heom_grid& g, int max_batch, int n_pw,
+                     const int* ops, double* Rdev) {
   const long long te = m->traj_elems();
   const int d = m->hm.d;
   const int n1 = g.n1, n3 = g.n3, sps = g.steps_per_sample;
@@ -564,10 +567,9 @@ void response_direct(heom_model* m, const heom_state* rho_eq, const heom_grid& g
   DevBuf snap(tb * n1);
   const int C = auto_batch(m, n1, sizeof(T), 3, 0, max_batch);
   DevBuf Z(tb * C), W1(tb * C), W2(tb * C);
-  const int pw_d[2][3] = {{HEOM_OP_MU_MINUS, HEOM_OP_MU_PLUS, HEOM_OP_MU_PLUS},
-                          {HEOM_OP_MU_PLUS, HEOM_OP_MU_MINUS, HEOM_OP_MU_PLUS}};
-  for (int P = 0; P < 2; ++P) {
-    t1_snapshots<T>(m, rho_eq, pw_d[P][0], pw_d[P][1], n1, sps, snap.as<T>());
+  for (int P = 0; P < n_pw; ++P) {
+    const int* pw = ops + 3 * P;
+    t1_snapshots<T>(m, rho_eq, pw[0], pw[1], n1, sps, snap.as<T>());
     for (int j0 = 0; j0 < n1; j0 += C) {
       const int c = std::min(C, n1 - j0);
       T* Y = snap.as<T>() + j0 * te;
@@ -575,11 +577,11 @@ void response_direct(heom_model* m, const heom_state* rho_eq, const heom_grid& g
       for (int i = 0; i < g.n_t2; ++i) {
         rk4_steps<T>(m, Y, W1.as<T>(), W2.as<T>(), c, g.t2_steps[i] - done, false);
         done = g.t2_steps[i];
-        heom::launch_commutator<T>(m->mu64[pw_d[P][2]].as<double>(), 0, Y, Z.as<T>(), d,
+        heom::launch_commutator<T>(m->mu64[pw[2]].as<double>(), 0, Y, Z.as<T>(), d,
                                    static_cast<long long>(c) * m->hm.n_ado, m->stream);
         for (int k = 0; k < n3; ++k) {
           if (k) rk4_steps<T>(m, Z.as<T>(), W1.as<T>(), W2.as<T>(), c, sps, false);
-          double* out = Rdev + 2 * ((((static_cast<long long>(i) * 2 + P) * n1 + j0) * n3) + k);
+          double* out = Rdev + 2 * ((((static_cast<long long>(i) * n_pw + P) * n1 + j0) * n3) + k);
           heom::launch_trace<T>(m->mu64[HEOM_OP_MU].as<double>(), Z.as<T>(), d, te, c, out, n3, m->stream);
         }
         check_finite<T>(m, Z.as<T>(), c, "t3 propagation");
@@ -589,14 +591,19 @@ void response_direct(heom_model* m, const heom_state* rho_eq, const heom_grid& g
 }
 
 template <typename T>
-void response_adjoint(heom_model* m, const heom_state* rho_eq, const heom_grid& g, int max_batch, double* Rdev) {
+void response_adjoint(heom_model* m, const heom_state* rho_eq, const heom_grid& g, int max_batch, int n_pw,
+                      const int* ops, double* Rdev) {
   const long long te = m->traj_elems();
   const int d = m->hm.d;
   const int n1 = g.n1, n3 = g.n3, sps = g.steps_per_sample;
   const size_t tb = static_cast<size_t>(te) * sizeof(T);
   // detection functional: l_0 = mu^T (n = 0 ADO), propagated with L^T;
-  // Psi_k = (D3^x)^T l(t3_k), D3 = mu_plus for both pathways.
-  DevBuf Psi(tb * n3);
+  // Psi_k = (D3^x)^T l(t3_k).  The samples l(t3_k) are kept only when the
+  // pathways use more than one D3.
+  bool one_d3 = true;
+  for (int P = 1; P < n_pw; ++P) one_d3 = one_d3 && ops[3 * P + 2] == ops[2];
+  DevBuf Psi(tb * n3), Lk;
+  if (!one_d3) Lk = DevBuf(tb * n3);
   {
     std::vector<double> h(static_cast<size_t>(te), 0.0);
     for (int a = 0; a < d; ++a)
@@ -606,8 +613,11 @@ void response_adjoint(heom_model* m, const heom_state* rho_eq, const heom_grid& 
     heom::launch_convert<double, T>(l64.as<double>(), l.as<T>(), te, m->stream);
     for (int k = 0; k < n3; ++k) {
       if (k) rk4_steps_scratch<T>(m, l.as<T>(), 1, sps, true);
-      heom::launch_commutator<T>(m->mu64[HEOM_OP_MU_PLUS].as<double>(), 1, l.as<T>(), Psi.as<T>() + k * te, d,
-                                 m->hm.n_ado, m->stream);
+      if (one_d3)
+        heom::launch_commutator<T>(m->mu64[ops[2]].as<double>(), 1, l.as<T>(), Psi.as<T>() + k * te, d,
+                                   m->hm.n_ado, m->stream);
+      else
+        hip_check(hipMemcpyAsync(Lk.as<T>() + k * te, l.p, tb, hipMemcpyDeviceToDevice, m->stream), "copy");
     }
     check_finite<T>(m, l.as<T>(), 1, "adjoint t3 scan");
   }
@@ -615,9 +625,15 @@ void response_adjoint(heom_model* m, const heom_state* rho_eq, const heom_grid& 
   const int C = auto_batch(m, n1, sizeof(T), 2, 0, max_batch);
   DevBuf W1(tb * C), W2(tb * C);
   DevBuf work(heom::pair_work_doubles(C, n3, m->hm.n_ado, d) * sizeof(double));
-  const int pw_d[2][2] = {{HEOM_OP_MU_MINUS, HEOM_OP_MU_PLUS}, {HEOM_OP_MU_PLUS, HEOM_OP_MU_MINUS}};
-  for (int P = 0; P < 2; ++P) {
-    t1_snapshots<T>(m, rho_eq, pw_d[P][0], pw_d[P][1], n1, sps, snap.as<T>());
+  int psi_op = one_d3 ? ops[2] : -1;
+  for (int P = 0; P < n_pw; ++P) {
+    const int* pw = ops + 3 * P;
+    if (pw[2] != psi_op) {
+      heom::launch_commutator<T>(m->mu64[pw[2]].as<double>(), 1, Lk.as<T>(), Psi.as<T>(), d,
+                                 static_cast<long long>(n3) * m->hm.n_ado, m->stream);
+      psi_op = pw[2];
+    }
+    t1_snapshots<T>(m, rho_eq, pw[0], pw[1], n1, sps, snap.as<T>());
     for (int j0 = 0; j0 < n1; j0 += C) {
       const int c = std::min(C, n1 - j0);
       T* Y = snap.as<T>() + j0 * te;
@@ -625,13 +641,58 @@ void response_adjoint(heom_model* m, const heom_state* rho_eq, const heom_grid& 
       for (int i = 0; i < g.n_t2; ++i) {
         rk4_steps<T>(m, Y, W1.as<T>(), W2.as<T>(), c, g.t2_steps[i] - done, false);
         done = g.t2_steps[i];
-        double* out = Rdev + 2 * (((static_cast<long long>(i) * 2 + P) * n1 + j0) * n3);
+        double* out = Rdev + 2 * (((static_cast<long long>(i) * n_pw + P) * n1 + j0) * n3);
         // R = i^3 <Psi_k, Y_j> = -i <.,.>
         heom::launch_pairing<T>(Y, c, Psi.as<T>(), n3, m->hm.n_ado, d, 0.0, -1.0, work.as<double>(), out,
                                 m->stream);
       }
       check_finite<T>(m, Y, c, "t2 propagation");
     }
+  }
+}
+
+// Rotating-wave pathways of heom_response_2d: I (rephasing) and II (non-rephasing).
+constexpr int kStdPathways[6] = {HEOM_OP_MU_MINUS, HEOM_OP_MU_PLUS, HEOM_OP_MU_PLUS,
+                                 HEOM_OP_MU_PLUS, HEOM_OP_MU_MINUS, HEOM_OP_MU_PLUS};
+
+void response_any(heom_model* m, const heom_state* rho_eq, const heom_grid* grid, int precision, int method,
+                  int max_batch, int n_pw, const int* ops, double* R_out) {
+  require_device(m);
+  require_state(m, rho_eq);
+  if (rho_eq->precision != HEOM_FP64 || rho_eq->n_traj != 1)
+    throw HeomError(HEOM_ERR_STATE, "rho_eq must be an FP64 state with one trajectory");
+  if (!grid || !R_out || !ops || n_pw < 1) throw HeomError(HEOM_ERR_PARAM, "null argument or no pathway");
+  for (int q = 0; q < 3 * n_pw; ++q)
+    if (ops[q] < HEOM_OP_MU || ops[q] > HEOM_OP_MU_MINUS) throw HeomError(HEOM_ERR_PARAM, "bad dipole operator");
+  const heom_grid& g = *grid;
+  if (g.n1 < 1 || g.n3 < 1 || g.steps_per_sample < 1 || g.n_t2 < 1 || !g.t2_steps)
+    throw HeomError(HEOM_ERR_PARAM, "bad grid");
+  for (int i = 0; i < g.n_t2; ++i)
+    if (g.t2_steps[i] < 0 || (i && g.t2_steps[i] < g.t2_steps[i - 1]))
+      throw HeomError(HEOM_ERR_PARAM, "t2_steps must be non-negative and non-decreasing");
+  if (method != HEOM_RESP_DIRECT && method != HEOM_RESP_ADJOINT) throw HeomError(HEOM_ERR_PARAM, "bad method");
+  const size_t n_out = static_cast<size_t>(g.n_t2) * n_pw * g.n1 * g.n3 * 2;
+  DevBuf Rdev(n_out * sizeof(double));
+  if (precision == HEOM_FP64) {
+    if (method == HEOM_RESP_DIRECT) response_direct<double>(m, rho_eq, g, max_batch, n_pw, ops, Rdev.as<double>());
+    else response_adjoint<double>(m, rho_eq, g, max_batch, n_pw, ops, Rdev.as<double>());
+  } else if (precision == HEOM_FP32) {
+    if (method == HEOM_RESP_DIRECT) response_direct<float>(m, rho_eq, g, max_batch, n_pw, ops, Rdev.as<double>());
+    else response_adjoint<float>(m, rho_eq, g, max_batch, n_pw, ops, Rdev.as<double>());
+  } else {
+    throw HeomError(HEOM_ERR_PARAM, "bad precision");
+  }
+  std::vector<double> h(n_out);
+  hip_check(hipMemcpyAsync(h.data(), Rdev.p, n_out * sizeof(double), hipMemcpyDeviceToHost, m->stream), "copy");
+  hip_check(hipStreamSynchronize(m->stream), "sync");
+  if (method == HEOM_RESP_DIRECT) {
+    // R = i^3 tr(...) = -i tr(...)
+    for (size_t q = 0; q < n_out / 2; ++q) {
+      R_out[2 * q] = h[2 * q + 1];
+      R_out[2 * q + 1] = -h[2 * q];
+    }
+  } else {
+    std::memcpy(R_out, h.data(), n_out * sizeof(double));
   }
 }
 
@@ -1759,43 +1820,12 @@ int heom_linear_response(heom_model* m, const heom_state* rho_eq, int n, int sps
 
 int heom_response_2d(heom_model* m, const heom_state* rho_eq, const heom_grid* grid, int precision, int method,
                      int max_batch, double* R_out) {
-  return guarded([&] {
-    require_device(m);
-    require_state(m, rho_eq);
-    if (rho_eq->precision != HEOM_FP64 || rho_eq->n_traj != 1)
-      throw HeomError(HEOM_ERR_STATE, "rho_eq must be an FP64 state with one trajectory");
-    if (!grid || !R_out) throw HeomError(HEOM_ERR_PARAM, "null argument");
-    const heom_grid& g = *grid;
-    if (g.n1 < 1 || g.n3 < 1 || g.steps_per_sample < 1 || g.n_t2 < 1 || !g.t2_steps)
-      throw HeomError(HEOM_ERR_PARAM, "bad grid");
-    for (int i = 0; i < g.n_t2; ++i)
-      if (g.t2_steps[i] < 0 || (i && g.t2_steps[i] < g.t2_steps[i - 1]))
-        throw HeomError(HEOM_ERR_PARAM, "t2_steps must be non-negative and non-decreasing");
-    if (method != HEOM_RESP_DIRECT && method != HEOM_RESP_ADJOINT) throw HeomError(HEOM_ERR_PARAM, "bad method");
-    const size_t n_out = static_cast<size_t>(g.n_t2) * 2 * g.n1 * g.n3 * 2;
-    DevBuf Rdev(n_out * sizeof(double));
-    if (precision == HEOM_FP64) {
-      if (method == HEOM_RESP_DIRECT) response_direct<double>(m, rho_eq, g, max_batch, Rdev.as<double>());
-      else response_adjoint<double>(m, rho_eq, g, max_batch, Rdev.as<double>());
-    } else if (precision == HEOM_FP32) {
-      if (method == HEOM_RESP_DIRECT) response_direct<float>(m, rho_eq, g, max_batch, Rdev.as<double>());
-      else response_adjoint<float>(m, rho_eq, g, max_batch, Rdev.as<double>());
-    } else {
-      throw HeomError(HEOM_ERR_PARAM, "bad precision");
-    }
-    std::vector<double> h(n_out);
-    hip_check(hipMemcpyAsync(h.data(), Rdev.p, n_out * sizeof(double), hipMemcpyDeviceToHost, m->stream), "copy");
-    hip_check(hipStreamSynchronize(m->stream), "sync");
-    if (method == HEOM_RESP_DIRECT) {
-      // R = i^3 tr(...) = -i tr(...)
-      for (size_t q = 0; q < n_out / 2; ++q) {
-        R_out[2 * q] = h[2 * q + 1];
-        R_out[2 * q + 1] = -h[2 * q];
-      }
-    } else {
-      std::memcpy(R_out, h.data(), n_out * sizeof(double));
-    }
-  });
+  return guarded([&] { response_any(m, rho_eq, grid, precision, method, max_batch, 2, kStdPathways, R_out); });
+}
+
+int heom_response_2d_pathways(heom_model* m, const heom_state* rho_eq, const heom_grid* grid, int precision,
+                              int method, int max_batch, int n_pathways, const int* ops, double* R_out) {
+  return guarded([&] { response_any(m, rho_eq, grid, precision, method, max_batch, n_pathways, ops, R_out); });
 }
 
 int heom_spectrum_2d(const double* R_I, const double* R_II, int n1, int n3, double dt_s, double* S_out) {
@@ -1839,6 +1869,26 @@ int heom_response_2d_vjp(heom_model* m, const heom_state* rho_eq, const heom_gri
     if (!heom::grad_supported(m->hm.d, m->hm.dims, m->hm.n_modes, kmax))
       throw HeomError(HEOM_ERR_PARAM, "gradient needs d <= 80, mode dimensions d_s <= 8 with d_s * d <= 512, and <= 4 terms per mode");
     response_vjp(m, rho_eq, g, W, rho_is_stationary != 0, tol, max_steps, out);
+  });
+}
+
+int heom_spectrum_1d(const double* R1, int n, double dt_s, double* I_out) {
+  return guarded([&] {
+    if (!R1 || !I_out || n < 1 || !(dt_s > 0)) throw HeomError(HEOM_ERR_PARAM, "bad arguments");
+    // I(W_m) = sum_k w_k dt_s exp(i W_m t_k) R1(t_k), W_m = 2 pi m / (2 n dt_s), m = -n..n-1
+    const double two_pi = 6.283185307179586476925287;
+    for (int mi = 0; mi < 2 * n; ++mi) {
+      const double W = two_pi * (mi - n) / (2.0 * n * dt_s);
+      std::complex<double> acc = 0.0;
+      for (int k = 0; k < n; ++k) {
+        const double ph = W * dt_s * k;
+        const std::complex<double> r(R1[2 * k], R1[2 * k + 1]);
+        acc += (k == 0 ? 0.5 : 1.0) * std::complex<double>(std::cos(ph), std::sin(ph)) * r;
+      }
+      acc *= dt_s;
+      I_out[2 * mi] = acc.real();
+      I_out[2 * mi + 1] = acc.imag();
+    }
   });
 }
 

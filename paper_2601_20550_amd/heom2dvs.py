@@ -119,6 +119,9 @@ _SIGS = {
                                        C.c_void_p]),
     "heom_response_2d": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(heom_grid), C.c_int,
                                    C.c_int, C.c_int, C.c_void_p]),
+    "heom_response_2d_pathways": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(heom_grid), C.c_int,
+                                            C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
+    "heom_spectrum_1d": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_void_p]),
     "heom_spectrum_2d": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_double,
                                    C.c_void_p]),
     "heom_response_2d_vjp": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(heom_grid), C.c_void_p,
@@ -432,6 +435,37 @@ def heom_response_2d(model, rho_eq: State, grid, precision="fp64", method="direc
                                  _METHOD[method], int(max_batch), _ptr(out)))
     z = out[0::2] + 1j * out[1::2]
     return z.reshape(n_t2, 2, grid["n1"], grid["n3"])
+
+
+def heom_response_2d_pathways(model, rho_eq: State, grid, pathways, precision="fp64", method="adjoint",
+                              max_batch=0):
+    """R[t2][pathway][t1][t3] (complex128) for dipole triples (D1, D2, D3), each
+    "mu", "mu_plus" or "mu_minus" (or a heom_operator value)."""
+    ops = []
+    for pw in pathways:
+        if len(pw) != 3:
+            raise ValueError("a pathway is a triple (D1, D2, D3)")
+        ops += [int(_OPS.get(x, x)) for x in pw]
+    arr = (C.c_int * len(ops))(*ops)
+    g, keep = _grid_struct(grid)
+    n_t2 = len(grid["t2_steps"])
+    out = np.zeros(n_t2 * len(pathways) * grid["n1"] * grid["n3"] * 2)
+    _check(_lib.heom_response_2d_pathways(model.handle, rho_eq.handle, C.byref(g), _PREC[precision],
+                                          _METHOD[method], int(max_batch), len(pathways), arr, _ptr(out)))
+    z = out[0::2] + 1j * out[1::2]
+    return z.reshape(n_t2, len(pathways), grid["n1"], grid["n3"])
+
+
+def heom_spectrum_1d(R1, dt_s):
+    """Linear line shape I(W) on the 2n frequency grid (complex128)."""
+    load_library()
+    R1 = np.asarray(R1, dtype=complex)
+    n = len(R1)
+    inp = np.zeros(2 * n)
+    inp[0::2], inp[1::2] = R1.real, R1.imag
+    out = np.zeros(4 * n)
+    _check(_lib.heom_spectrum_1d(_ptr(inp), n, float(dt_s), _ptr(out)))
+    return out[0::2] + 1j * out[1::2]
 
 
 def heom_spectrum_2d(R_I, R_II, dt_s):

@@ -49,7 +49,7 @@ def _relerr(a, b):
     return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
 
 
-CASES = [("cfg1", None), ("cfg2", None), ("cfg2", 2), ("cfg3", 2)]
+CASES = [("cfg1", None), ("cfg2", None), ("cfg2", 2), ("cfg3", 2), ("paper_scale", 2)]
 
 
 KERNELS = ["generic", "mfma", "mfma_dyn"]
@@ -217,7 +217,7 @@ def _response_case(which, depth, n, sps, t2, dt=None):
 
 
 RESP = [("cfg1", None, 8, 25, [0, 40], None), ("cfg2", 2, 6, 5, [0, 12], None),
-        ("cfg3", 1, 4, 4, [0, 6], None)]
+        ("cfg3", 1, 4, 4, [0, 6], None), ("paper_scale", 1, 3, 3, [0, 4], None)]
 
 
 @pytest.mark.parametrize("which,depth,n,sps,t2,dt", RESP)
@@ -362,3 +362,33 @@ def test_krylov_equilibration_three_modes_is_stationary():
     assert np.max(np.abs(oh.rhs(o, got))) < 1e-10
     assert abs(np.trace(got[0]) - 1.0) < 1e-12
     assert np.max(np.abs(got[0] - got[0].conj().T)) < 1e-10
+
+
+PATHWAYS = [("mu", "mu", "mu"),                  # full response, all 8 Liouville terms
+            ("mu_plus", "mu_plus", "mu_minus"),  # double-quantum (k1 + k2 - k3)
+            ("mu_minus", "mu_plus", "mu_plus")]  # rephasing, as in heom_response_2d
+
+
+@pytest.mark.parametrize("method", ["direct", "adjoint"])
+def test_response_pathways_parity(method):
+    params = _params("cfg2", 2)
+    o = om.build(params)
+    m = P.heom_model_build(params)
+    rho_ref = oh.propagate(o, oh.ground_state_hierarchy(o), 50)
+    rho = P.State(m, 1, "fp64")
+    rho.upload(rho_ref[None])
+    grid = {"n1": 4, "n3": 5, "steps_per_sample": 4, "t2_steps": [0, 6]}
+    names = {"mu": o.mu, "mu_plus": o.mu_plus, "mu_minus": o.mu_minus}
+    ref = oh.response_2d(o, rho_ref, grid,
+                         pathways=[tuple(names[x] for x in pw) for pw in PATHWAYS])
+    got = P.heom_response_2d_pathways(m, rho, grid, PATHWAYS, "fp64", method)
+    assert got.shape == ref.shape
+    assert _relerr(got, ref) < 1e-10
+    got32 = P.heom_response_2d_pathways(m, rho, grid, PATHWAYS, "fp32", method)
+    assert _relerr(got32, ref) < 1e-4
+    # the standard call is the rephasing / non-rephasing pair of this one
+    std = P.heom_response_2d(m, rho, grid, "fp64", method)
+    assert _relerr(got[:, 2], std[:, 0]) < 1e-13
+    with pytest.raises(P.heom2dvs.HeomError) as e:
+        P.heom_response_2d_pathways(m, rho, grid, [(0, 1, 7)], "fp64", method)
+    assert e.value.code == P.heom2dvs.HEOM_ERR_PARAM

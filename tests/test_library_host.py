@@ -133,3 +133,14 @@ def test_params_vjp_matches_oracle_directions():
     got = P.heom_params_vjp(params, dirs, g)
     ref = np.array([og.contract(g, og.operator_directions_fd(params, dr)) for dr in dirs])
     assert np.max(np.abs(got - ref)) < 1e-7 * np.max(np.abs(ref))
+
+
+def test_spectrum_1d_matches_oracle():
+    from oracle import heom as oh
+    rng = np.random.default_rng(6)
+    for n, dt_s in ((8, 0.5), (13, 1.0)):
+        R1 = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        got = P.heom_spectrum_1d(R1, dt_s)
+        ref = oh.linear_spectrum(R1, dt_s)
+        assert got.shape == (2 * n,)
+        assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))

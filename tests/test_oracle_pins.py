@@ -451,6 +451,20 @@ def test_spectrum_geometric_series():
     assert S.shape == (2 * n3, 2 * n1)
 
 
+def test_linear_spectrum_geometric_series():
+    # R1(t_k) = exp(-(c + i a) t_k): the trapezoid-weighted sum is
+    # dt ((1 - r^n)/(1 - r) - 1/2) with r = exp((i (W - a) - c) dt)
+    n, dts, a, c = 11, 0.6, 0.9, 0.05
+    t = dts * np.arange(n)
+    R1 = np.exp(-(c + 1j * a) * t)
+    W = heom.frequency_grid(n, dts)
+    r = np.exp((1j * (W - a) - c) * dts)
+    ex = dts * ((1 - r ** n) / (1 - r) - 0.5)
+    got = heom.linear_spectrum(R1, dts)
+    np.testing.assert_allclose(got, ex, atol=1e-12)
+    assert got.shape == (2 * n,)
+
+
 @pytest.mark.slow
 def test_correlation_spectrum_sign_convention():
     # Strongly anharmonic oscillator: the 0->1->0 diagonal peak (near w10, w10)

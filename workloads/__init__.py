@@ -17,6 +17,7 @@ from .configs import (  # noqa: F401
     theta_directions,
     theta_size,
     harmonic_pin,
+    paper_scale,
     fs_to_steps,
     response_grid,
 )

@@ -245,3 +245,23 @@ def cfg5_small(seed: int = 0):
               "decomp": "pade", "dt": 0.1}
     r = rng.choice([-1.0, 1.0], size=theta_size(params))
     return params, response_grid(6, 4, [0, 8]), [float(1.0 + 0.05 * x) for x in r]
+
+
+def paper_scale(seed: int = 0, depth: int = 5, temperature_k: float = 300.0):
+    """The hierarchy scale of the paper's own water runs: three modes (sym,
+    asym stretch, bend; 1 : 1.03 : 0.44) kept at 4 levels each (d = 64), K = 4
+    Pade terms per mode (15 exponential terms), depth 5 (15,504 ADOs); the
+    temperature is an assumption (300 K: beta hbar omega0 = 3470 / 208.5);
+    other parameters drawn as in cfg3; dt = 0.1, 64 x 64 grid at t2 = 0."""
+    rng = np.random.default_rng(seed + 500)
+    modes = [_mode(rng, 1.0, n_keep=4, K=4), _mode(rng, 1.03, n_keep=4, K=4),
+             _mode(rng, 0.44, n_keep=4, K=4)]
+    g01, g02, g12 = (float(x) for x in rng.uniform(0.0, 0.05, size=3))
+    f02, f12 = (float(x) for x in rng.uniform(0.0, 0.05, size=2))
+    couplings = [_coupling(0, 1, g_st=g01, mu_st=0.02),
+                 _coupling(0, 2, g_st=g02, g_st2=f02, mu_st=0.02),
+                 _coupling(1, 2, g_st=g12, g_st2=f12, mu_st=0.02)]
+    beta = 3470.0 / (0.69503476 * float(temperature_k))
+    params = {"modes": modes, "couplings": couplings, "beta": beta,
+              "depth": int(depth), "decomp": "pade", "dt": 0.1}
+    return params, response_grid(64, 10, [0])
