@@ -392,3 +392,83 @@ def test_response_pathways_parity(method):
     with pytest.raises(P.heom2dvs.HeomError) as e:
         P.heom_response_2d_pathways(m, rho, grid, [(0, 1, 7)], "fp64", method)
     assert e.value.code == P.heom2dvs.HEOM_ERR_PARAM
+
+
+def _edge_params(kind):
+    p = _params("cfg2")
+    if kind == "depth0":            # a single ADO: the system alone, no bath couplings
+        p["depth"] = 0
+    elif kind == "drude_only":      # K = 0: only the Drude term of each bath
+        p["depth"] = 2
+        for md in p["modes"]:
+            md["K"] = 0
+    elif kind == "no_bath":         # zeta = 0: every bath coefficient vanishes
+        p["depth"] = 2
+        for md in p["modes"]:
+            md["zeta"] = 0.0
+    elif kind == "max_d":           # d = 8 x 16 = 128, the largest product dimension
+        p["depth"] = 1
+        p["modes"][0]["n_keep"] = 8
+        p["modes"][1]["n_keep"] = 16
+        p["modes"][1]["n_basis"] = 20
+    elif kind == "max_mfma32":      # d = 7 x 16 = 112, the largest FP32 matrix-core size
+        p["depth"] = 1
+        p["modes"][0]["n_keep"] = 7
+        p["modes"][1]["n_keep"] = 16
+        p["modes"][1]["n_basis"] = 20
+    return p
+
+
+@pytest.mark.parametrize("kind", ["depth0", "drude_only", "no_bath", "max_d", "max_mfma32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rhs_parity_edge_models(kind, prec):
+    params = _edge_params(kind)
+    o = om.build(params)
+    m = P.heom_model_build(params)
+    x = w.random_hierarchy(2, len(o.hier), o.d, seed=17, scale_by_depth=_depth_scale(o))
+    kernels = ["generic", "mfma"]
+    # the matrix-core kernels stage three DP x (DP+1) planes in 160 KB of LDS:
+    # d <= 112 in FP32, d <= 80 in FP64
+    if kind == "max_d" or (kind == "max_mfma32" and prec == "fp64"):
+        kernels = ["generic"]
+        with pytest.raises(P.heom2dvs.HeomError) as e:
+            P.heom_model_set_kernel(m, prec, "mfma")
+        assert e.value.code == P.heom2dvs.HEOM_ERR_PARAM
+    for kernel in kernels:
+        P.heom_model_set_kernel(m, prec, kernel)
+        for adjoint in (False, True):
+            xin, xout = P.State(m, 2, prec), P.State(m, 2, prec)
+            xin.upload(x)
+            P.heom_rhs(m, xin, xout, adjoint)
+            ref = oh.rhs(o, x, adjoint=adjoint)
+            tol = 1e-12 if prec == "fp64" else 4e-6
+            assert _relerr(xout.download(), ref) < tol, (kernel, adjoint)
+
+
+def test_response_2d_without_bath_hierarchy():
+    # depth 0: the response of the isolated system, against the oracle
+    params = _edge_params("depth0")
+    o = om.build(params)
+    m = P.heom_model_build(params)
+    rho_ref = oh.propagate(o, oh.ground_state_hierarchy(o), 10)
+    rho = P.State(m, 1, "fp64")
+    rho.upload(rho_ref[None])
+    grid = {"n1": 4, "n3": 4, "steps_per_sample": 3, "t2_steps": [0, 5]}
+    ref = oh.response_2d(o, rho_ref, grid)
+    for method in ("direct", "adjoint"):
+        assert _relerr(P.heom_response_2d(m, rho, grid, "fp64", method), ref) < 1e-10
+
+
+def test_empty_and_zero_work_requests():
+    m = P.heom_model_build(_params("cfg1"))
+    with pytest.raises(P.heom2dvs.HeomError) as e:
+        P.State(m, 0, "fp64")
+    assert e.value.code == P.heom2dvs.HEOM_ERR_PARAM
+    s = P.State(m, 2, "fp32")
+    s.set_ground()
+    before = s.download()
+    P.heom_propagate(m, s, 0)
+    assert np.array_equal(s.download(), before)
+    with pytest.raises(P.heom2dvs.HeomError) as e:
+        P.heom_propagate(m, s, -1)
+    assert e.value.code == P.heom2dvs.HEOM_ERR_PARAM
