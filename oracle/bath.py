@@ -1,4 +1,8 @@
-"""Drude-bath correlation as a sum of exponentials (oracle).
+"""Bath correlations as sums of exponentials (oracle; test infrastructure).
+
+Drude baths follow the paper directly; underdamped Brownian baths (the HEOM
+admits other spectral densities, Sec. II.B) use the same residue construction
+and are defined in brownian_terms below.
 
 Paper, Sec. II.B: for the Drude spectral density the bath correlation is a sum
 of decaying exponentials.  The fluctuation part needs the expansion of
@@ -138,3 +142,87 @@ def drude_terms(zeta, gamma, beta, K, decomp="pade"):
         nus.append(float(n))
         cs.append(complex(-(zeta * gamma ** 2 / beta) * 2 * e * n / (gamma ** 2 - n ** 2), 0.0))
     return np.array(nus), np.array(cs)
+
+
+def bra_coefficients(nu, c):
+    """Coefficients of the conjugate correlation on the same exponentials.
+
+    C(t)* = sum_j conj(c_j) exp(-conj(nu_j) t); written over the terms
+    exp(-nu_j t) of C(t) it reads sum_j cb_j exp(-nu_j t) with
+    cb_j = conj(c_j') where nu_j' = conj(nu_j).  The hierarchy's bra-side
+    coupling uses cb_j (Theta_j X = c_j V X - cb_j X V); for real rates
+    cb_j = conj(c_j) (Eqs. Pade1, Pade2), for a complex-conjugate pair of rates
+    the two terms swap their conjugated coefficients.
+    """
+    nu = np.asarray(nu, dtype=complex)
+    c = np.asarray(c, dtype=complex)
+    cb = np.empty_like(c)
+    for j in range(len(nu)):
+        partner = [i for i in range(len(nu)) if abs(nu[i] - np.conj(nu[j])) <= 1e-12 * (1 + abs(nu[j]))]
+        if len(partner) != 1:
+            raise ValueError("exponential rates must be distinct and closed under conjugation")
+        cb[j] = np.conj(c[partner[0]])
+    return cb
+
+
+def brownian_density(w, zeta, gamma, omega_b):
+    """Underdamped Brownian spectral density in the normalisation of the Drude one:
+
+    J(w) = (zeta/pi) gamma^2 omega_b^2 w / ((omega_b^2 - w^2)^2 + gamma^2 w^2),
+
+    whose int_0^inf J(w)/w dw = zeta gamma / 2 equals the Drude Lambda (so the
+    counter term is unchanged), and which becomes the Drude density of cutoff
+    omega_b^2/gamma and the same Lambda when gamma >> omega_b.
+    """
+    return zeta / np.pi * gamma ** 2 * omega_b ** 2 * w / ((omega_b ** 2 - w * w) ** 2 + gamma ** 2 * w * w)
+
+
+def brownian_terms(zeta, gamma, omega_b, beta, K, decomp="pade"):
+    """Exponential terms (nu_j, c_j), j = 0..K+1, of one Brownian bath.
+
+    C(t) = int_0^inf J(w) [coth(beta w/2) cos wt - i sin wt] dw with coth
+    replaced by its decomposition (Pade [K-1/K] or K Matsubara terms) is, for
+    t > 0, the sum of the residues of J(w) (1 + coth(beta w/2))/2 exp(-i w t)
+    in the lower half plane (the same construction that gives Eqs. Pade1 and
+    Pade2 for the Drude density):
+
+      * the two poles w_p of J, rate nu_p = i w_p (a complex-conjugate pair
+        gamma/2 +- i sqrt(omega_b^2 - gamma^2/4) when underdamped),
+        c_p = -2 pi i Res_{w_p} J (1 + coth(beta w_p/2))/2;
+      * the poles w = -i xi_k/beta of the coth decomposition, rate
+        nu_k = xi_k/beta, c_k = -2 pi i (eta_k/beta) J(-i nu_k).
+
+    Returns complex arrays (nu, c).  Raises ValueError at critical damping
+    (omega_b = gamma/2, a double pole) or when a rate coincides with a pole.
+    """
+    xi, eta = (pade_poles(K) if decomp == "pade" else matsubara_poles(K))
+    if abs(omega_b ** 2 - gamma ** 2 / 4) < 1e-12:
+        raise ValueError("critically damped Brownian density (double pole)")
+    A = zeta / np.pi * gamma ** 2 * omega_b ** 2
+    # J(w) = A w / prod_i (w - w_i), w_i the roots of w^4 + (gamma^2 - 2 omega_b^2) w^2 + omega_b^4
+    roots = np.roots([1.0, 0.0, gamma ** 2 - 2 * omega_b ** 2, 0.0, omega_b ** 4]).astype(complex)
+
+    def coth_dec(x):
+        return 2.0 / x + sum(4 * e * x / (x * x + s * s) for s, e in zip(xi, eta))
+
+    nus, cs = [], []
+    for p, wp in enumerate(roots):
+        if wp.imag >= 0:
+            continue
+        res = A * wp / np.prod([wp - wi for i, wi in enumerate(roots) if i != p])
+        nus.append(1j * wp)
+        cs.append(-2j * np.pi * res * 0.5 * (1.0 + coth_dec(beta * wp)))
+    if len(nus) != 2:
+        raise ValueError("Brownian density needs omega_b > 0, gamma > 0")
+    order = np.argsort([n.imag for n in nus])[::-1]
+    nus = [nus[i] for i in order]
+    cs = [cs[i] for i in order]
+    for s, e in zip(xi, eta):
+        nk = s / beta
+        den = (omega_b ** 2 + nk * nk) ** 2 - gamma ** 2 * nk * nk
+        if abs(den) < 1e-12 or any(abs(nk - n) < 1e-12 for n in nus):
+            raise ValueError("a Brownian rate coincides with a low-temperature pole")
+        Jk = A * (-1j * nk) / den
+        nus.append(complex(nk))
+        cs.append(-2j * np.pi * (e / beta) * Jk)
+    return np.array(nus, dtype=complex), np.array(cs, dtype=complex)

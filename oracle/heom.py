@@ -4,11 +4,15 @@ Hierarchy states are complex arrays of shape (..., N_ado, d, d); leading axes
 are independent trajectories.  Everything is double precision.
 
 Right-hand side (Eq. HEOM_DB with Theta_j from Eqs. Pade1/Pade2 written as
-Theta_j X = c_j V X - conj(c_j) X V, see oracle.bath):
+Theta_j X = c_j V X - cb_j X V, see oracle.bath):
 
   d rho_n/dt = -i (H rho_n - rho_n H) - (sum_j n_j nu_j) rho_n
-               - i sum_j n_j (c_j V_s(j) rho_{n-e_j} - conj(c_j) rho_{n-e_j} V_s(j))
+               - i sum_j n_j (c_j V_s(j) rho_{n-e_j} - cb_j rho_{n-e_j} V_s(j))
                - i sum_j (V_s(j) rho_{n+e_j} - rho_{n+e_j} V_s(j)),
+
+where cb_j = conj(c_j) for the real rates of a Drude bath and, for the
+complex-conjugate pair of rates of a Brownian bath, the conjugated
+coefficient of the partner term (bath.bra_coefficients).
 
 with ADOs outside the index set treated as zero.  Time stepping is the classic
 four-stage Runge-Kutta method with a fixed step (Sec. III).
@@ -55,11 +59,12 @@ def rhs(model: Model, rho, adjoint: bool = False):
     <A, X> = sum_n sum_ab A_n[a, b] X_n[a, b]; with H and V_s real symmetric
     it moves the n_j c_j factor from the lower to the upper neighbour:
       (L^T A)_m = -i H^x A_m - gamma_m A_m - i sum_j V^x A_{m-e_j}
-                  - i sum_j (m_j + 1)(c_j V A_{m+e_j} - conj(c_j) A_{m+e_j} V).
+                  - i sum_j (m_j + 1)(c_j V A_{m+e_j} - cb_j A_{m+e_j} V).
     """
     H = model.H
     hier = model.hier
     out = -1j * (H @ rho - rho @ H) - model.gamma_sum[:, None, None] * rho
+    cb = model.c_bra
     for j in range(hier.n_terms):
         V = model.V[model.term_mode[j]]
         cj = model.c[j]
@@ -72,13 +77,13 @@ def rhs(model: Model, rho, adjoint: bool = False):
             out[..., mu_, :, :] += -1j * (V @ X - X @ V)
             Y = rho[..., dn[md_], :, :]
             nj = hier.n[md_, j][:, None, None]
-            out[..., md_, :, :] += -1j * nj * (cj * (V @ Y) - np.conj(cj) * (Y @ V))
+            out[..., md_, :, :] += -1j * nj * (cj * (V @ Y) - cb[j] * (Y @ V))
         else:
             Y = rho[..., dn[md_], :, :]
             out[..., md_, :, :] += -1j * (V @ Y - Y @ V)
             X = rho[..., up[mu_], :, :]
             nj = (hier.n[mu_, j] + 1)[:, None, None]
-            out[..., mu_, :, :] += -1j * nj * (cj * (V @ X) - np.conj(cj) * (X @ V))
+            out[..., mu_, :, :] += -1j * nj * (cj * (V @ X) - cb[j] * (X @ V))
     return out
 
 
@@ -117,6 +122,7 @@ def liouvillian_matrix(model: Model, adjoint: bool = False):
     VL = [sp.kron(sp.csr_matrix(V), I) for V in model.V]
     VR = [sp.kron(I, sp.csr_matrix(V.T)) for V in model.V]
     blocks = [[None] * N for _ in range(N)]
+    cb = model.c_bra
     for i in range(N):
         blocks[i][i] = -1j * Hc - model.gamma_sum[i] * sp.identity(d * d)
         for j in range(hier.n_terms):
@@ -127,7 +133,7 @@ def liouvillian_matrix(model: Model, adjoint: bool = False):
                 blk = -1j * (VL[s] - VR[s])
                 blocks[i][up] = blk if blocks[i][up] is None else blocks[i][up] + blk
             if dn >= 0:
-                blk = -1j * hier.n[i, j] * (cj * VL[s] - np.conj(cj) * VR[s])
+                blk = -1j * hier.n[i, j] * (cj * VL[s] - cb[j] * VR[s])
                 blocks[i][dn] = blk if blocks[i][dn] is None else blocks[i][dn] + blk
     Lm = sp.bmat(blocks, format="csr")
     return Lm.T.tocsr() if adjoint else Lm

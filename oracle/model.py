@@ -116,12 +116,13 @@ class Model:
     mu_plus: np.ndarray
     mu_minus: np.ndarray
     term_mode: np.ndarray         # mode of each exponential term j
-    nu: np.ndarray                # nu_j
+    nu: np.ndarray                # nu_j (real, or complex for a Brownian bath)
     c: np.ndarray                 # c_j (complex)
     hier: Hierarchy
     dt: float = 0.01
     dims: tuple = ()
     modes: list = field(default_factory=list)
+    cb: np.ndarray = None         # bra-side coefficients; None means conj(c)
 
     @property
     def d(self):
@@ -132,9 +133,18 @@ class Model:
         """sum_j n_j nu_j for every ADO."""
         return self.hier.n @ self.nu
 
+    @property
+    def c_bra(self):
+        """Coefficients of the bra-side coupling (conj(c) for real rates)."""
+        return np.conj(self.c) if self.cb is None else self.cb
 
-def make_model(H, V, mu, term_mode, nu, c, depth, dt=0.01, dims=None, modes=None):
-    """Assemble a Model from explicit operators (used by engine-level checks)."""
+
+def make_model(H, V, mu, term_mode, nu, c, depth, dt=0.01, dims=None, modes=None, cb=None):
+    """Assemble a Model from explicit operators (used by engine-level checks).
+
+    Complex rates nu_j (Brownian baths) need the bra-side coefficients cb;
+    by default they are derived from (nu, c) by bath.bra_coefficients.
+    """
     d = H.shape[0]
     dims = tuple(dims) if dims is not None else (d,)
     if int(np.prod(dims)) != d:
@@ -143,11 +153,17 @@ def make_model(H, V, mu, term_mode, nu, c, depth, dt=0.01, dims=None, modes=None
     mu = np.asarray(mu, dtype=float)
     mu_plus = np.where(N[:, None] > N[None, :], mu, 0.0)
     hier = Hierarchy(len(nu), depth)
+    nu = np.asarray(nu, dtype=complex)
+    c = np.asarray(c, dtype=complex)
+    if np.all(nu.imag == 0):
+        nu = nu.real.copy()
+        cb = None if cb is None else np.asarray(cb, dtype=complex)
+    elif cb is None:
+        cb = bath.bra_coefficients(nu, c)
     return Model(H=np.asarray(H, dtype=float), V=[np.asarray(v, dtype=float) for v in V],
                  mu=mu, mu_plus=mu_plus, mu_minus=mu_plus.T.copy(),
                  term_mode=np.asarray(term_mode, dtype=np.int64),
-                 nu=np.asarray(nu, dtype=float), c=np.asarray(c, dtype=complex),
-                 hier=hier, dt=dt, dims=dims, modes=list(modes or []))
+                 nu=nu, c=c, hier=hier, dt=dt, dims=dims, modes=list(modes or []), cb=cb)
 
 
 def flip_sign(m: ModeOps, i: int) -> ModeOps:
@@ -187,8 +203,12 @@ def build_from_modes(params, modes) -> Model:
     V = [embed({s: m.v}, dims) for s, m in enumerate(modes)]
     term_mode, nus, cs = [], [], []
     for s, p in enumerate(params["modes"]):
-        nu, c = bath.drude_terms(p["zeta"], p["gamma"], params["beta"], int(p["K"]),
-                                 params.get("decomp", "pade"))
+        if p.get("omega_b", 0.0) > 0.0:
+            nu, c = bath.brownian_terms(p["zeta"], p["gamma"], p["omega_b"], params["beta"],
+                                        int(p["K"]), params.get("decomp", "pade"))
+        else:
+            nu, c = bath.drude_terms(p["zeta"], p["gamma"], params["beta"], int(p["K"]),
+                                     params.get("decomp", "pade"))
         term_mode += [s] * len(nu)
         nus += list(nu)
         cs += list(c)

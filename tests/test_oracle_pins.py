@@ -95,6 +95,74 @@ def test_bath_correlation_matches_fdt_integral():
     assert err(2, 2.0) > err(4, 2.0) > err(12, 2.0)
 
 
+def test_brownian_density_normalisation_and_overdamped_limit():
+    # int J/w dw = zeta gamma / 2 (the Drude Lambda, so the counter term is
+    # shared); for gamma >> omega_b the density is the Drude one of cutoff
+    # omega_b^2/gamma with the same Lambda.
+    zeta, gamma, wb = 0.1, 0.5, 2.0
+    lam = si.quad(lambda x: bath.brownian_density(x, zeta, gamma, wb) / x, 0, np.inf, limit=400)[0]
+    assert lam == pytest.approx(zeta * gamma / 2, rel=1e-9)
+    g, wb2 = 400.0, 2.0
+    G = wb2 ** 2 / g
+    zd = zeta * g / G
+    x = np.array([0.01, 0.1, 0.3, 1.0])
+    drude = zd / np.pi * G ** 2 * x / (x * x + G ** 2)
+    np.testing.assert_allclose(bath.brownian_density(x, zeta, g, wb2), drude, rtol=1e-3)
+
+
+@pytest.mark.parametrize("gamma,wb", [(0.2, 1.0), (0.5, 2.0), (3.0, 1.0)])
+def test_brownian_correlation_matches_fdt_integral(gamma, wb):
+    # C(t) = int_0^inf J(w) [coth(beta w/2) cos wt - i sin wt] dw for the
+    # Brownian density, by quadrature: (i) with coth replaced by the very
+    # decomposition the terms use, the residue sum is exact for t > 0;
+    # (ii) with the exact coth, K = 12 Pade terms converge to it; (iii) the
+    # imaginary part has the closed form -(zeta gamma wb^2/(2 r)) e^{-gamma t/2}
+    # sin(r t), r = sqrt(wb^2 - gamma^2/4) (a sinh for the overdamped case).
+    zeta, beta = 0.1, 10.0
+
+    def J(x):
+        return bath.brownian_density(x, zeta, gamma, wb)
+
+    def re_part(t, coth):
+        def f(x):
+            return 2.0 / beta * J(1e-300) / 1e-300 if x == 0 else J(x) * coth(x)
+        return si.quad(f, 0, np.inf, weight="cos", wvar=t, limlst=400, limit=400)[0]
+
+    r = np.sqrt(complex(wb ** 2 - gamma ** 2 / 4))
+    xi2, eta2 = bath.pade_poles(2)
+    nu2, c2 = bath.brownian_terms(zeta, gamma, wb, beta, 2, "pade")
+    nu12, c12 = bath.brownian_terms(zeta, gamma, wb, beta, 12, "pade")
+    scale = np.max(np.abs(c12))
+    for t in (1.0, 3.0, 7.0):
+        im_closed = np.real(-(zeta * gamma * wb ** 2 / (2 * r)) * np.exp(-gamma * t / 2) * np.sin(r * t))
+        im_quad = -si.quad(J, 0, np.inf, weight="sin", wvar=t, limlst=400, limit=400)[0]
+        assert abs(im_quad - im_closed) < 1e-7 * scale
+        for nu, c in ((nu2, c2), (nu12, c12)):
+            C = np.sum(c * np.exp(-nu * t))
+            assert abs(C.imag - im_closed) < 1e-13 * scale
+        # coth_approx(beta w) is the decomposed coth(beta w / 2)
+        dec = re_part(t, lambda x: bath.coth_approx(np.array([beta * x]), xi2, eta2)[0])
+        assert abs(np.sum(c2 * np.exp(-nu2 * t)).real - dec) < 1e-8 * scale
+        exact = re_part(t, lambda x: 1.0 / np.tanh(beta * x / 2))
+        assert abs(np.sum(c12 * np.exp(-nu12 * t)).real - exact) < 1e-6 * scale
+    # C(0) is real: the imaginary parts of the pair cancel
+    assert abs(np.sum(c12).imag) < 1e-15 * scale
+
+
+def test_bra_coefficients_pairing():
+    nu, c = bath.brownian_terms(0.1, 0.2, 1.0, 10.0, 2)
+    cb = bath.bra_coefficients(nu, c)
+    assert abs(nu[0] - np.conj(nu[1])) < 1e-15
+    assert cb[0] == np.conj(c[1]) and cb[1] == np.conj(c[0])
+    np.testing.assert_array_equal(cb[2:], np.conj(c[2:]))
+    np.testing.assert_array_equal(bath.bra_coefficients(nu, cb), c)
+    nd, cd = bath.drude_terms(0.1, 0.2, 10.0, 3)
+    np.testing.assert_array_equal(bath.bra_coefficients(nd, cd), np.conj(cd))
+    # C(t)* = sum_j cb_j exp(-nu_j t)
+    for t in (0.5, 2.0):
+        assert abs(np.conj(np.sum(c * np.exp(-nu * t))) - np.sum(cb * np.exp(-nu * t))) < 1e-16
+
+
 def test_bath_singular_gamma_rejected():
     xi, _ = bath.pade_poles(2)
     with pytest.raises(ValueError):
@@ -172,17 +240,29 @@ def _small_model():
     return om.build(p)
 
 
-def test_rhs_matches_assembled_liouvillian():
-    m = _small_model()
+def _brownian_model(depth=3):
+    p, _ = w.cfg1()
+    p["modes"][0]["omega_b"] = 1.5
+    p["modes"][0]["gamma"] = 0.4
+    p["depth"] = depth
+    p["decomp"] = "pade"
+    return om.build(p)
+
+
+@pytest.mark.parametrize("bath_kind", ["drude", "brownian"])
+def test_rhs_matches_assembled_liouvillian(bath_kind):
+    m = _small_model() if bath_kind == "drude" else _brownian_model()
     x = w.random_hierarchy(1, len(m.hier), m.d, seed=3)[0]
     Lm = heom.liouvillian_matrix(m)
     np.testing.assert_allclose(Lm @ x.reshape(-1), heom.rhs(m, x).reshape(-1), atol=1e-13)
 
 
-@pytest.mark.parametrize("cfg", ["cfg1", "cfg2small"])
+@pytest.mark.parametrize("cfg", ["cfg1", "cfg2small", "brownian"])
 def test_adjoint_dot_product(cfg):
     if cfg == "cfg1":
         m = _small_model()
+    elif cfg == "brownian":
+        m = _brownian_model()
     else:
         p, _ = w.cfg2()
         p["depth"] = 2
@@ -319,14 +399,20 @@ def test_no_bath_response_is_sum_over_states():
                     assert abs(R[i, pidx, j, k] - ex) < 1e-6 * (1 + abs(ex))
 
 
-def test_pure_dephasing_cumulant():
+@pytest.mark.parametrize("bath_kind", ["drude", "brownian"])
+def test_pure_dephasing_cumulant(bath_kind):
     # Diagonal H and V: rho_ab(t) = rho_ab(0) exp(-i w_ab t)
     #   * exp[-(v_a - v_b)(v_a g(t) - v_b conj(g(t)))],
     # g(t) = sum_j c_j (exp(-nu_j t) + nu_j t - 1)/nu_j^2 (second-order
     # cumulant, exact for a Gaussian bath); the hierarchy converges to it.
+    # The Brownian bath has a complex-conjugate pair of rates, whose bra-side
+    # couplings carry the partner's conjugated coefficient.
     eps = np.array([0.0, 1.0, 1.9])
     v = np.array([0.0, 0.6, 1.3])
-    nu, c = bath.drude_terms(0.1, 0.5, 2.0, 3, "pade")
+    if bath_kind == "drude":
+        nu, c = bath.drude_terms(0.1, 0.5, 2.0, 3, "pade")
+    else:
+        nu, c = bath.brownian_terms(0.1, 0.5, 1.2, 2.0, 2, "pade")
     errs = []
     for L in (4, 8):
         m = om.make_model(np.diag(eps), [np.diag(v)], np.zeros((3, 3)),
@@ -373,6 +459,54 @@ def test_harmonic_linear_response_is_brownian_oscillator(beta, K, decomp):
     ex = np.array([_chi_brownian(t, 1.0, 0.2, 0.1, 1.0) for t in np.arange(16.0)])
     assert np.max(np.abs(R1.imag)) < 1e-12
     assert np.max(np.abs(R1.real - ex)) < 2e-5
+
+
+def _chi_brownian_bath(t, omega0, gamma, zeta, V1, wb):
+    # friction kernel of the Brownian density: xi(s) = zeta gamma (s + gamma)/(s^2 + gamma s + wb^2);
+    # chi(s) = 1/(s^2 + w0^2 + V1^2 s xi(s)), inverted over the four poles
+    num = np.array([1.0, gamma, wb * wb])
+    den = np.polyadd(np.polymul([1.0, 0.0, omega0 ** 2], num),
+                     V1 * V1 * zeta * gamma * np.array([1.0, gamma, 0.0]))
+    poles = np.roots(den)
+    tot = 0.0
+    for i, s in enumerate(poles):
+        dd = np.prod([s - q for k, q in enumerate(poles) if k != i])
+        tot = tot + np.polyval(num, s) / dd * np.exp(s * t)
+    return np.real(tot)
+
+
+def test_brownian_bath_closed_form_against_langevin_ode():
+    # the same chi(t) as the impulse response of the Langevin equation
+    # x'' + w0^2 x + V1^2 int xi(t - u) x'(u) du = 0, x(0) = 0, x'(0) = 1, with
+    # the kernel realised by an auxiliary damped oscillator g'' + gamma g' +
+    # wb^2 g = x', friction force zeta gamma (g' + gamma g)
+    w0, gamma, zeta, V1, wb = 1.0, 0.5, 0.1, 1.0, 2.0
+
+    def f(t, u):
+        x, y, g, h = u
+        return [y, -w0 ** 2 * x - V1 ** 2 * zeta * gamma * (h + gamma * g), h, y - gamma * h - wb ** 2 * g]
+
+    ts = np.arange(16.0)
+    sol = si.solve_ivp(f, (0, 15.0), [0.0, 1.0, 0.0, 0.0], t_eval=ts, rtol=1e-12, atol=1e-14,
+                       method="DOP853")
+    ex = np.array([_chi_brownian_bath(t, w0, gamma, zeta, V1, wb) for t in ts])
+    assert np.max(np.abs(sol.y[0] - ex)) < 1e-10
+
+
+@pytest.mark.parametrize("beta,K,decomp", [(10.0, 2, "pade"), (10.0, 2, "matsubara"),
+                                           (3.0, 1, "pade")])
+def test_harmonic_linear_response_brownian_bath(beta, K, decomp):
+    # Harmonic mode coupled to an underdamped Brownian bath (complex rates):
+    # R1(t) = chi(t) of the Langevin equation with the Brownian friction
+    # kernel, independent of beta and K; R1 stays real.
+    p = w.harmonic_pin(depth=4, K=K, dt=0.02, n_keep=6, beta=beta, decomp=decomp,
+                       gamma=0.5, omega_b=2.0)
+    m = om.build(p)
+    assert np.any(np.abs(np.imag(m.nu)) > 0)
+    R1 = heom.linear_response(m, heom.ground_state_hierarchy(m), 16, 50)
+    ex = np.array([_chi_brownian_bath(t, 1.0, 0.5, 0.1, 1.0, 2.0) for t in np.arange(16.0)])
+    assert np.max(np.abs(R1.imag)) < 1e-12
+    assert np.max(np.abs(R1.real - ex)) < 1e-5
 
 
 def test_harmonic_third_order_response_vanishes():

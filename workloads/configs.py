@@ -162,11 +162,14 @@ def cfg5(seed: int = 0):
 
 
 def harmonic_pin(omega=1.0, zeta=0.1, gamma=0.2, V1=1.0, beta=10.0, K=2,
-                 depth=4, n_keep=6, decomp="pade", dt=0.01):
-    """Harmonic mode with linear (LL) coupling and a linear dipole."""
+                 depth=4, n_keep=6, decomp="pade", dt=0.01, omega_b=0.0):
+    """Harmonic mode with linear (LL) coupling and a linear dipole (Drude
+    bath, or a Brownian bath of frequency omega_b when omega_b > 0)."""
     m = {"omega": omega, "g3": 0.0, "g4": 0.0, "V1": V1, "V2": 0.0,
          "zeta": zeta, "gamma": gamma, "mu1": 1.0, "mu2": 0.0,
          "n_basis": 12, "n_keep": n_keep, "K": K}
+    if omega_b > 0.0:
+        m["omega_b"] = float(omega_b)
     return {"modes": [m], "couplings": [], "beta": beta, "depth": depth,
             "decomp": decomp, "dt": dt}
 
