@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 # scaled by the counters' readings for kernels of known size.  Keyed by the
 # kernel source hash: a changed kernel reports traffic null until re-profiled.
 PROFILED_TRAFFIC = {
-    "45c707127383ddd4": {"read_GB": 286.1, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
+    "2750103b784ea559": {"read_GB": 286.3, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
 }
 
 PEAKS = {  # MI355X published dense peaks
@@ -176,9 +176,11 @@ def main():
     ap.add_argument("--multi", type=int, default=1,
                     help="1: also time the 64-instance uneven batch; 2: and one instance at a time")
     ap.add_argument("--grad", type=int, default=1, help="also time the reverse-mode gradient")
-    ap.add_argument("--workload", default="cfg3", choices=["cfg3", "paper"],
+    ap.add_argument("--workload", default="cfg3", choices=["cfg3", "paper", "brownian"],
                     help="cfg3: 3-mode, 80 states, depth 6 (5005 ADOs); paper: the paper's hierarchy "
-                         "scale, 3 x 4 levels, K = 4 Pade, depth 5 (15,504 ADOs), 300 K assumed")
+                         "scale, 3 x 4 levels, K = 4 Pade, depth 5 (15,504 ADOs), 300 K assumed; "
+                         "brownian: cfg3's modes with Brownian baths (complex rate pairs), "
+                         "12 terms, depth 5 (6188 ADOs)")
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "mfma", "mfma_dyn"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -193,6 +195,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "paper":
         params, grid = w.paper_scale()
+    elif args.workload == "brownian":
+        params, grid = w.cfg3_brownian()
     else:
         params, grid = w.cfg3(depth=args.depth)
     stream = torch.cuda.current_stream()
@@ -239,10 +243,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic (seeded water-like 3-mode model; no trained inputs)",
-        "config": {"workload": (f"3-mode MAB HEOM, 80 states, K=2 Pade x3, depth {args.depth} "
-                                if args.workload == "cfg3" else
-                                f"3-mode MAB HEOM at the paper's scale, 64 states, K=4 Pade x3, depth "
-                                f"{params['depth']}, 300 K assumed ")
+        "config": {"workload": ({"cfg3": f"3-mode MAB HEOM, 80 states, K=2 Pade x3, depth {args.depth} ",
+                                 "paper": "3-mode MAB HEOM at the paper's scale, 64 states, K=4 Pade x3, "
+                                          f"depth {params['depth']}, 300 K assumed ",
+                                 "brownian": "3-mode MAB HEOM, 80 states, Brownian baths (omega_b 0.25, "
+                                             f"K=2 Pade) x3, depth {params['depth']} "}[args.workload])
                                + f"({m.n_ado} ADOs), {B} trajectories batched, RK4 dt=0.1",
                    "n_ado": m.n_ado, "d": m.d, "trajectories": B},
         "roofline": {"bound": "alu" if kernel == "generic" else "mfma", "achieved": achieved,

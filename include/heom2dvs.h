@@ -70,10 +70,19 @@ typedef enum { HEOM_RESP_DIRECT = 0, HEOM_RESP_ADJOINT = 1 } heom_resp_method;
  *   V_s(q) = V1 q + V2 q^2/2                             (Eq. h_int, LL + SL)
  *   Drude bath (zeta, gamma) with K low-temperature terms (Eqs. drude, Pade1/2)
  *   dipole mu1 q + mu2 q^2/2                             (Eq. NLdip, s = s')
- *   n_basis harmonic levels are diagonalised, n_keep eigenstates are kept. */
+ *   n_basis harmonic levels are diagonalised, n_keep eigenstates are kept.
+ * omega_b > 0 replaces the Drude density by the Brownian (underdamped
+ * oscillator) density J(w) = (zeta/pi) gamma^2 omega_b^2 w /
+ * ((omega_b^2 - w^2)^2 + gamma^2 w^2), one of the other spectral densities the
+ * HEOM admits (Sec. II.B); it has the Drude counter-term constant zeta gamma/2
+ * and K + 2 exponential terms: a complex-conjugate pair of rates
+ * gamma/2 +- i sqrt(omega_b^2 - gamma^2/4) (two real rates when overdamped)
+ * followed by the K low-temperature terms.  omega_b = gamma/2 (critical
+ * damping) is rejected with HEOM_ERR_PARAM. */
 typedef struct {
   double omega, g3, g4, V1, V2, zeta, gamma, mu1, mu2;
   int n_basis, n_keep, K;
+  double omega_b;                   /* 0 = Drude bath                        */
 } heom_mode;
 
 /* Mode-mode coupling (Eq. Potential ss') and cross dipole (Eq. NLdip), s < t:
@@ -147,6 +156,14 @@ int heom_model_info(const heom_model* model, heom_info* out);
 int heom_model_operators(const heom_model* model, double* H, double* mu, double* mu_plus,
                          double* mu_minus, double* v, double* nu, double* c, int* ado_n,
                          int* term_mode);
+/* Exponential terms of the bath correlations, C(t) = sum_j c_j exp(-nu_j t)
+ * per mode, with the bra-side coefficients c_bra_j of the coupling
+ * Theta_j X = c_j V X - c_bra_j X V: the coefficient of exp(-nu_j t) in
+ * C(t)*, i.e. conj(c_j) for a real rate and the partner's conj(c) for a
+ * complex-conjugate pair of rates (Brownian baths).  Each output [n_terms]
+ * complex (interleaved doubles), may be NULL.  heom_model_operators' nu
+ * holds the real parts. */
+int heom_model_bath(const heom_model* model, double* nu, double* c, double* c_bra);
 
 /* -------------------------------------------------------------- state -- */
 /* A device hierarchy of n_traj independent trajectories (n_traj x n_ado
@@ -298,8 +315,8 @@ typedef struct {
  * RK4 steps (stationary_steps / stationary_residual report them;
  * HEOM_ERR_NOCONV if not reached); 0: rho_eq is held fixed.  W: host
  * [n_t2][2][n1][n3] complex.  Needs d <= 80, every mode dimension d_s <= 8
- * with d_s * d <= 512, and K + 1 <= 4 terms per mode (HEOM_ERR_PARAM
- * otherwise). */
+ * with d_s * d <= 512, K + 1 <= 4 terms per mode, and Drude baths (real
+ * rates; HEOM_ERR_PARAM otherwise). */
 int heom_response_2d_vjp(heom_model* model, const heom_state* rho_eq, const heom_grid* grid, const double* W,
                          int rho_is_stationary, double tol, int max_steps, heom_op_grad* out);
 
@@ -312,7 +329,8 @@ int heom_spectrum_2d_vjp(const double* G, int n1, int n3, double dt_s, double* W
  * operator entries of g x d(operators)/d(params) along dirs[i], the
  * derivative of the host model build taken by central differences with the
  * given step (dirs[i] has the layout of params and holds the derivative of
- * every number; integer fields are ignored).  Host computation. */
+ * every number; integer fields are ignored).  Host computation.  Drude
+ * baths only (omega_b = 0 in every mode; HEOM_ERR_PARAM otherwise). */
 int heom_params_vjp(const heom_params* params, const heom_params* dirs, int n_dirs, double step,
                     const heom_op_grad* g, double* out);
 

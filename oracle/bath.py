@@ -214,7 +214,8 @@ def brownian_terms(zeta, gamma, omega_b, beta, K, decomp="pade"):
         cs.append(-2j * np.pi * res * 0.5 * (1.0 + coth_dec(beta * wp)))
     if len(nus) != 2:
         raise ValueError("Brownian density needs omega_b > 0, gamma > 0")
-    order = np.argsort([n.imag for n in nus])[::-1]
+    # the pair in the order (+Im, -Im); two real (overdamped) rates ascending
+    order = sorted(range(2), key=lambda i: (-nus[i].imag, nus[i].real))
     nus = [nus[i] for i in order]
     cs = [cs[i] for i in order]
     for s, e in zip(xi, eta):

@@ -159,7 +159,12 @@ def make_model(H, V, mu, term_mode, nu, c, depth, dt=0.01, dims=None, modes=None
         nu = nu.real.copy()
         cb = None if cb is None else np.asarray(cb, dtype=complex)
     elif cb is None:
-        cb = bath.bra_coefficients(nu, c)
+        # each bath's correlation is conjugated on its own terms
+        tm = np.asarray(term_mode)
+        cb = np.empty_like(c)
+        for s in np.unique(tm):
+            sel = tm == s
+            cb[sel] = bath.bra_coefficients(nu[sel], c[sel])
     return Model(H=np.asarray(H, dtype=float), V=[np.asarray(v, dtype=float) for v in V],
                  mu=mu, mu_plus=mu_plus, mu_minus=mu_plus.T.copy(),
                  term_mode=np.asarray(term_mode, dtype=np.int64),

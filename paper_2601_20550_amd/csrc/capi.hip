@@ -131,7 +131,7 @@ struct heom_model {
   hipStream_t stream = nullptr;
   int lds_limit = 65536;
   // device copies
-  DevBuf H64, H32, v64, v32, g64, g32, mu64[3];
+  DevBuf H64, H32, v64, v32, g64, g32, gi64, gi32, mu64[3];
   DevBuf Hp64, Hp32;  // H zero-padded to a multiple of 16 (matrix-core kernel)
   int kernel[2] = {HEOM_KERNEL_MFMA, HEOM_KERNEL_MFMA};  // per precision
   DevBuf nb_ptr[2], nb_idx[2], nb_a64[2], nb_a32[2];
@@ -224,6 +224,10 @@ void upload_model(heom_model* m) {
   m->v32 = f32(vpack);
   m->g64 = upload_vec(hm.gamma_sum, st);
   m->g32 = f32(hm.gamma_sum);
+  if (hm.complex_rates) {
+    m->gi64 = upload_vec(hm.gamma_sum_im, st);
+    m->gi32 = f32(hm.gamma_sum_im);
+  }
   m->mu64[HEOM_OP_MU] = upload_vec(hm.mu, st);
   m->mu64[HEOM_OP_MU_PLUS] = upload_vec(hm.mu_plus, st);
   m->mu64[HEOM_OP_MU_MINUS] = upload_vec(hm.mu_minus, st);
@@ -240,11 +244,13 @@ void upload_model(heom_model* m) {
     }
     m->nb_a64[dir] = upload_vec(a, st);
     m->nb_a32[dir] = f32(a);
-    auto fill = [&](auto& op, const DevBuf& H, const DevBuf& v, const DevBuf& g, const DevBuf& na) {
+    auto fill = [&](auto& op, const DevBuf& H, const DevBuf& v, const DevBuf& g, const DevBuf& gi,
+                    const DevBuf& na) {
       using T = std::remove_const_t<std::remove_pointer_t<decltype(op.H)>>;
       op.H = H.as<T>();
       op.v = v.as<T>();
       op.gamma = g.as<T>();
+      op.gamma_im = hm.complex_rates ? gi.as<T>() : nullptr;
       op.nb_ptr = m->nb_ptr[dir].as<int>();
       op.nb_idx = m->nb_idx[dir].as<int>();
       op.nb_a = na.as<T>();
@@ -257,8 +263,8 @@ void upload_model(heom_model* m) {
       op.d = hm.d;
       op.n_ado = hm.n_ado;
     };
-    fill(m->ops64[dir], m->H64, m->v64, m->g64, m->nb_a64[dir]);
-    fill(m->ops32[dir], m->H32, m->v32, m->g32, m->nb_a32[dir]);
+    fill(m->ops64[dir], m->H64, m->v64, m->g64, m->gi64, m->nb_a64[dir]);
+    fill(m->ops32[dir], m->H32, m->v32, m->g32, m->gi32, m->nb_a32[dir]);
   }
   {
     const int d = hm.d, DP = 16 * ((d + 15) / 16);
@@ -1476,6 +1482,27 @@ int heom_model_operators(const heom_model* m, double* H, double* mu, double* mu_
   });
 }
 
+int heom_model_bath(const heom_model* m, double* nu, double* c, double* c_bra) {
+  return guarded([&] {
+    if (!m) throw HeomError(HEOM_ERR_PARAM, "null model");
+    const auto& hm = m->hm;
+    for (int j = 0; j < hm.n_terms; ++j) {
+      if (nu) {
+        nu[2 * j] = hm.nu[j];
+        nu[2 * j + 1] = hm.nu_im[j];
+      }
+      if (c) {
+        c[2 * j] = hm.c[j].real();
+        c[2 * j + 1] = hm.c[j].imag();
+      }
+      if (c_bra) {
+        c_bra[2 * j] = hm.cb[j].real();
+        c_bra[2 * j + 1] = hm.cb[j].imag();
+      }
+    }
+  });
+}
+
 int heom_state_create(heom_model* m, int n_traj, int precision, heom_state** out) {
   return guarded([&] {
     require_device(m);
@@ -1868,6 +1895,9 @@ int heom_response_2d_vjp(heom_model* m, const heom_state* rho_eq, const heom_gri
     }
     if (!heom::grad_supported(m->hm.d, m->hm.dims, m->hm.n_modes, kmax))
       throw HeomError(HEOM_ERR_PARAM, "gradient needs d <= 80, mode dimensions d_s <= 8 with d_s * d <= 512, and <= 4 terms per mode");
+    for (int j = 0; j < m->hm.n_terms; ++j)
+      if (m->hm.nu_im[j] != 0.0 || m->hm.cb[j] != std::conj(m->hm.c[j]))
+        throw HeomError(HEOM_ERR_PARAM, "gradient supports Drude baths only (real rates, bra coefficients conj(c))");
     response_vjp(m, rho_eq, g, W, rho_is_stationary != 0, tol, max_steps, out);
   });
 }
@@ -1936,6 +1966,9 @@ int heom_params_vjp(const heom_params* params, const heom_params* dirs, int n_di
     if (!params || !dirs || n_dirs < 0 || !g || !out || !(step > 0))
       throw HeomError(HEOM_ERR_PARAM, "bad arguments");
     const heom_params base = copy_check(params);
+    for (int s = 0; s < base.n_modes; ++s)
+      if (base.modes && base.modes[s].omega_b != 0.0)
+        throw HeomError(HEOM_ERR_PARAM, "parameter gradient supports Drude baths only");
     for (int i = 0; i < n_dirs; ++i) {
       const heom_params& dp = dirs[i];
       if (dp.n_modes != base.n_modes || dp.n_couplings != base.n_couplings)

@@ -12,7 +12,8 @@ template <typename T>
 struct DevOps {
   const T* H;          // d x d
   const T* v;          // per mode dims[s]^2, packed
-  const T* gamma;      // per ADO: sum_j n_j nu_j
+  const T* gamma;      // per ADO: Re sum_j n_j nu_j
+  const T* gamma_im;   // per ADO: Im sum_j n_j nu_j, or null when every rate is real
   const int* nb_ptr;   // n_ado * n_modes + 1
   const int* nb_idx;
   const T* nb_a;

@@ -26,6 +26,7 @@ inline void check_launch(const char* what) {
 //
 //   L(rho)_n = -i (H rho_n - rho_n H) - gamma_n rho_n
 //              - i sum_s (V_s X_s - Y_s V_s),
+//   gamma_n = sum_j n_j nu_j (complex when a bath has complex rates),
 //   X_s = sum_{m in nb(n,s)} aL_m rho_m,  Y_s = sum_{m in nb(n,s)} aR_m rho_m,
 //
 // where the neighbour lists and coefficients (from the host tables) encode the
@@ -82,6 +83,11 @@ __global__ __launch_bounds__(NT) void rhs_generic_kernel(DevOps<T> op, const T* 
       for (int k = 0; k < d; ++k) s += H[a * d + k] * sm[k * d + c] - sm[a * d + k] * H[k * d + c];
       accI[i] = -s - g * rin[dd + e];
       accR[i] -= g * sm[e];
+      if (op.gamma_im) {  // complex rates: -(g + i gi) rho
+        const T gi = op.gamma_im[n];
+        accR[i] += gi * rin[dd + e];
+        accI[i] -= gi * sm[e];
+      }
     }
   }
   // couplings to the hierarchy neighbours through V_s

@@ -7,11 +7,13 @@
 // and computes every term of those outputs:
 //
 //   L rho = -i (H rho - rho H) - gamma_n rho + sum_s [ -i V_s X_s + i Y_s V_s ],
-//   X_s = sum_q aL_q rho_{m_q},   Y_s = sum_q conj(aL_q) rho_{m_q}
-//       = X_s - 2i sum_q Im(aL_q) rho_{m_q},
+//   X_s = sum_q aL_q rho_{m_q},   Y_s = sum_q aR_q rho_{m_q}
+//       = X_s + sum_q (aR_q - aL_q) rho_{m_q},
 //
 // with H real symmetric, V_s = v_s acting on mode s only, and the neighbour
-// lists (m_q, aL_q) of the host tables (aR = conj(aL) for every entry).
+// lists (m_q, aL_q, aR_q) of the host tables; aR = conj(aL) for Drude baths,
+// so only the entries with complex coefficients enter the second sum, and
+// gamma_n = sum_j n_j nu_j is complex only for complex rates (Brownian baths).
 //
 //   * H rho and rho H run on v_mfma 16x16x4 (FP32 or FP64): the fragment
 //     H[row block w][k-slice] stays in registers; rho (two real planes) and
@@ -252,8 +254,9 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
     // keep the scheduler from hoisting the LDS operands of many k-slices
     __builtin_amdgcn_sched_barrier(0);
   }
-  // damping
+  // damping -(g + i gi) rho; gi != 0 only for complex rates (Brownian baths)
   const T g = op.gamma[n];
+  const T gi = op.gamma_im ? op.gamma_im[n] : T(0);
 #pragma unroll
   for (int jj = 0; jj < JT; ++jj)
 #pragma unroll
@@ -262,6 +265,10 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
       if (j0 + jj < NB) {
         Rre[jj][r] -= g * sRe[a * LD + c];
         Rim[jj][r] -= g * sIm[a * LD + c];
+        if (gi != T(0)) {
+          Rre[jj][r] += gi * sIm[a * LD + c];
+          Rim[jj][r] -= gi * sRe[a * LD + c];
+        }
       }
     }
 
@@ -283,7 +290,7 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
       for (int q = p0; q < p1; ++q) {
         const T* rm = in + traj_base + static_cast<long long>(op.nb_idx[q]) * 2 * dd + srow0 * d;
         const T ar = op.nb_a[4 * q], ai = op.nb_a[4 * q + 1];
-        have_w = have_w || ai != T(0);
+        have_w = have_w || op.nb_a[4 * q + 2] != ar || op.nb_a[4 * q + 3] != ai;
         const bool first = q == p0;
 #pragma unroll
         for (int k = 0; k < RV; ++k) {
@@ -323,7 +330,9 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
       for (int q = p0; q < p1; ++q) {
         const T* rm = in + traj_base + static_cast<long long>(op.nb_idx[q]) * 2 * dd + srow0 * d;
         const T ar = op.nb_a[4 * q], ai = op.nb_a[4 * q + 1];
-        const bool cplx = ai != T(0);
+        // W accumulates Y_s - X_s = sum_q (aR_q - aL_q) rho_q
+        const T dr = op.nb_a[4 * q + 2] - ar, di = op.nb_a[4 * q + 3] - ai;
+        const bool cplx = dr != T(0) || di != T(0);
         have_w = have_w || cplx;
 #pragma unroll
         for (int k = 0; k < RV; ++k) {
@@ -334,8 +343,8 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
             xr[k] += ar * br - ai * bi;
             xi[k] += ar * bi + ai * br;
             if (cplx) {
-              wr[k] += ai * br;
-              wi[k] += ai * bi;
+              wr[k] += dr * br - di * bi;
+              wi[k] += dr * bi + di * br;
             }
           }
         }
@@ -387,8 +396,8 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
             const int r = srow0 + e / d, c = e - (e / d) * d;
 #pragma unroll
             for (int i = 0; i < VW; ++i) {
-              sRe[r * LD + c + i] = vget<T, VW>(xr[k], i) + 2 * vget<T, VW>(wi[k], i);
-              sIm[r * LD + c + i] = vget<T, VW>(xi[k], i) - 2 * vget<T, VW>(wr[k], i);
+              sRe[r * LD + c + i] = vget<T, VW>(xr[k], i) + vget<T, VW>(wr[k], i);
+              sIm[r * LD + c + i] = vget<T, VW>(xi[k], i) + vget<T, VW>(wi[k], i);
             }
           }
         }
@@ -420,15 +429,14 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
           }
         }
       }
-      // Y_s = X_s - 2i sum_q Im(aL_q) rho_q on the slab rows: a second pass
-      // over the neighbours with complex coefficients
+      // Y_s = X_s + sum_q (aR_q - aL_q) rho_q on the slab rows: a second
+      // pass over the neighbours whose bra coefficient differs
       if (have_w) {
         __syncthreads();  // left products read other waves' rows
         for (int q = p0; q < p1; ++q) {
-          const T ai = op.nb_a[4 * q + 1];
-          if (ai == T(0)) continue;
+          const T dr = op.nb_a[4 * q + 2] - op.nb_a[4 * q], di = op.nb_a[4 * q + 3] - op.nb_a[4 * q + 1];
+          if (dr == T(0) && di == T(0)) continue;
           const T* rm = in + traj_base + static_cast<long long>(op.nb_idx[q]) * 2 * dd + srow0 * d;
-          const T a2 = 2 * ai;
 #pragma unroll
           for (int k = 0; k < RV; ++k) {
             const int e = (lane + 64 * k) * VW;
@@ -438,8 +446,8 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
               const int r = srow0 + e / d, c = e - (e / d) * d;
 #pragma unroll
               for (int i = 0; i < VW; ++i) {
-                sRe[r * LD + c + i] += a2 * vget<T, VW>(bi, i);
-                sIm[r * LD + c + i] -= a2 * vget<T, VW>(br, i);
+                sRe[r * LD + c + i] += dr * vget<T, VW>(br, i) - di * vget<T, VW>(bi, i);
+                sIm[r * LD + c + i] += dr * vget<T, VW>(bi, i) + di * vget<T, VW>(br, i);
               }
             }
           }

@@ -36,12 +36,16 @@ struct HostModel {
   std::vector<int> quanta;                       // per product state
   int n_terms = 0;
   std::vector<int> term_mode;
-  std::vector<double> nu;
+  std::vector<double> nu;                        // Re nu_j
+  std::vector<double> nu_im;                     // Im nu_j (Brownian pairs)
   std::vector<cplx> c;
+  std::vector<cplx> cb;                          // bra-side coefficients
+  bool complex_rates = false;                    // some Im nu_j != 0
   int n_ado = 0;
   std::vector<int> ado_n;                        // n_ado * n_terms
   std::vector<int> ado_depth;
-  std::vector<double> gamma_sum;                 // sum_j n_j nu_j
+  std::vector<double> gamma_sum;                 // Re sum_j n_j nu_j
+  std::vector<double> gamma_sum_im;              // Im sum_j n_j nu_j
   Neighbours fwd, adj;
 };
 

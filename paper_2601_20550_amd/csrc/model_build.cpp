@@ -255,6 +255,8 @@ HostModel build_host_model(const heom_params& p) {
       throw std::invalid_argument("mode " + std::to_string(s) + ": need 1 <= n_keep <= n_basis <= 64");
     if (m.K < 0 || m.K > 16) throw std::invalid_argument("K must be 0..16");
     if (!(m.gamma > 0.0) || m.zeta < 0.0) throw std::invalid_argument("need gamma > 0, zeta >= 0");
+    if (m.omega_b < 0.0 || !std::isfinite(m.omega_b))
+      throw std::invalid_argument("mode " + std::to_string(s) + ": omega_b must be >= 0 (0 = Drude bath)");
     mb.push_back(diagonalise_mode(m));
     hm.dims[s] = m.n_keep;
   }
@@ -310,6 +312,49 @@ HostModel build_host_model(const heom_params& p) {
       }
     }
     const double g = m.gamma, z = m.zeta, beta = p.beta;
+    auto add_term = [&](cplx nu, cplx c, cplx cb) {
+      hm.term_mode.push_back(s);
+      hm.nu.push_back(nu.real());
+      hm.nu_im.push_back(nu.imag());
+      hm.c.push_back(c);
+      hm.cb.push_back(cb);
+    };
+    if (m.omega_b > 0.0) {
+      // Brownian density J(w) = (zeta/pi) gamma^2 wb^2 w / ((wb^2 - w^2)^2 + gamma^2 w^2):
+      // the two lower-half-plane poles w = +-r - i gamma/2 of J give the rates
+      // nu = gamma/2 +- i r with r = sqrt(wb^2 - gamma^2/4) (imaginary when
+      // overdamped) and c = +-(zeta gamma wb^2 / (4 r)) (coth(beta w/2) + 1), the
+      // coth taken in its decomposed form; the decomposition's poles give real
+      // rates xi_k/beta with c_k = -(2 zeta gamma^2 wb^2/beta) eta_k nu_k /
+      // ((wb^2 + nu_k^2)^2 - gamma^2 nu_k^2).
+      const double wb = m.omega_b;
+      const cplx r = std::sqrt(cplx(wb * wb - 0.25 * g * g, 0.0));
+      if (std::abs(r) < 1e-6) throw std::invalid_argument("mode " + std::to_string(s) + ": critically damped Brownian bath");
+      auto coth_dec = [&](cplx x) {
+        cplx v = 2.0 / x;
+        for (size_t k = 0; k < xi.size(); ++k) v += 4.0 * eta[k] * x / (x * x + xi[k] * xi[k]);
+        return v;
+      };
+      const cplx pref = z * g * wb * wb / (4.0 * r);
+      const cplx w1 = r - cplx(0.0, 0.5 * g), w2 = -r - cplx(0.0, 0.5 * g);
+      const cplx nu1 = cplx(0.0, 1.0) * w1, nu2 = cplx(0.0, 1.0) * w2;
+      const cplx c1 = pref * (coth_dec(beta * w1) + 1.0);
+      const cplx c2 = -pref * (coth_dec(beta * w2) + 1.0);
+      // bra side: C(t)* puts conj(c1) on exp(-conj(nu1) t); for a conjugate
+      // pair that is the partner's rate, for two real rates its own
+      const bool pair = std::fabs(nu1.imag()) > 0.0;
+      add_term(nu1, c1, pair ? std::conj(c2) : std::conj(c1));
+      add_term(nu2, c2, pair ? std::conj(c1) : std::conj(c2));
+      for (size_t k = 0; k < xi.size(); ++k) {
+        const double nk = xi[k] / beta;
+        const double den = (wb * wb + nk * nk) * (wb * wb + nk * nk) - g * g * nk * nk;
+        if (std::fabs(den) < 1e-12 || std::abs(nu1 - nk) < 1e-12 || std::abs(nu2 - nk) < 1e-12)
+          throw std::invalid_argument("mode " + std::to_string(s) + ": a Brownian rate coincides with a low-temperature pole");
+        const double ck = -(2.0 * z * g * g * wb * wb / beta) * eta[k] * nk / den;
+        add_term(nk, ck, ck);
+      }
+      continue;
+    }
     double sum = 1.0;
     for (int k = 0; k < m.K; ++k) {
       double nk = xi[k] / beta;
@@ -317,16 +362,15 @@ HostModel build_host_model(const heom_params& p) {
         throw std::invalid_argument("mode " + std::to_string(s) + ": gamma coincides with a low-temperature pole");
       sum += 2.0 * eta[k] * g * g / (g * g - nk * nk);
     }
-    hm.term_mode.push_back(s);
-    hm.nu.push_back(g);
-    hm.c.push_back(cplx(z * g / beta * sum, -0.5 * z * g * g));
+    const cplx c0(z * g / beta * sum, -0.5 * z * g * g);
+    add_term(g, c0, std::conj(c0));
     for (int k = 0; k < m.K; ++k) {
       double nk = xi[k] / beta;
-      hm.term_mode.push_back(s);
-      hm.nu.push_back(nk);
-      hm.c.push_back(cplx(-(z * g * g / beta) * 2.0 * eta[k] * nk / (g * g - nk * nk), 0.0));
+      const cplx ck(-(z * g * g / beta) * 2.0 * eta[k] * nk / (g * g - nk * nk), 0.0);
+      add_term(nk, ck, std::conj(ck));
     }
   }
+  for (double x : hm.nu_im) hm.complex_rates = hm.complex_rates || x != 0.0;
   hm.n_terms = static_cast<int>(hm.nu.size());
   const int M = hm.n_terms;
   // hierarchy
@@ -348,16 +392,19 @@ HostModel build_host_model(const heom_params& p) {
   hm.ado_n.resize(static_cast<size_t>(hm.n_ado) * M);
   hm.ado_depth.resize(hm.n_ado);
   hm.gamma_sum.resize(hm.n_ado);
+  hm.gamma_sum_im.resize(hm.n_ado);
   for (int i = 0; i < hm.n_ado; ++i) {
     int dep = 0;
-    double gs = 0.0;
+    double gs = 0.0, gi = 0.0;
     for (int j = 0; j < M; ++j) {
       hm.ado_n[static_cast<size_t>(i) * M + j] = ados[i][j];
       dep += ados[i][j];
       gs += ados[i][j] * hm.nu[j];
+      gi += ados[i][j] * hm.nu_im[j];
     }
     hm.ado_depth[i] = dep;
     hm.gamma_sum[i] = gs;
+    hm.gamma_sum_im[i] = gi;
   }
   // neighbour lists, grouped by mode
   auto build_nb = [&](Neighbours& nb, bool adjoint) {
@@ -381,7 +428,7 @@ HostModel build_host_model(const heom_params& p) {
               nb.aR.push_back(1.0);
             } else {
               nb.aL.push_back(static_cast<double>(nj + 1) * hm.c[j]);
-              nb.aR.push_back(static_cast<double>(nj + 1) * std::conj(hm.c[j]));
+              nb.aR.push_back(static_cast<double>(nj + 1) * hm.cb[j]);
             }
           }
           // lower neighbour n - e_j
@@ -392,7 +439,7 @@ HostModel build_host_model(const heom_params& p) {
             nb.tj.push_back(nj);
             if (!adjoint) {
               nb.aL.push_back(static_cast<double>(nj) * hm.c[j]);
-              nb.aR.push_back(static_cast<double>(nj) * std::conj(hm.c[j]));
+              nb.aR.push_back(static_cast<double>(nj) * hm.cb[j]);
             } else {
               nb.aL.push_back(1.0);
               nb.aR.push_back(1.0);

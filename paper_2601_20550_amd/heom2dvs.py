@@ -49,7 +49,8 @@ class HeomError(RuntimeError):
 class heom_mode(C.Structure):
     _fields_ = [(n, C.c_double) for n in
                 ("omega", "g3", "g4", "V1", "V2", "zeta", "gamma", "mu1", "mu2")] + \
-               [("n_basis", C.c_int), ("n_keep", C.c_int), ("K", C.c_int)]
+               [("n_basis", C.c_int), ("n_keep", C.c_int), ("K", C.c_int),
+                ("omega_b", C.c_double)]
 
 
 class heom_coupling(C.Structure):
@@ -93,6 +94,7 @@ _SIGS = {
     "heom_model_free": (None, [C.c_void_p]),
     "heom_model_info": (C.c_int, [C.c_void_p, C.POINTER(heom_info)]),
     "heom_model_operators": (C.c_int, [C.c_void_p] + [C.c_void_p] * 9),
+    "heom_model_bath": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "heom_state_create": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_void_p)]),
     "heom_state_free": (None, [C.c_void_p]),
     "heom_state_shape": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
@@ -187,6 +189,7 @@ def _params_struct(params):
         arr[i].n_basis = int(m["n_basis"])
         arr[i].n_keep = int(m["n_keep"])
         arr[i].K = int(m["K"])
+        arr[i].omega_b = float(m.get("omega_b", 0.0))
     cps = params.get("couplings", [])
     carr = (heom_coupling * max(1, len(cps)))()
     for i, c in enumerate(cps):
@@ -288,6 +291,10 @@ class Model:
             off += ds * ds
         return {"H": H, "mu": mu, "mu_plus": mup, "mu_minus": mum, "v": vs, "nu": nu,
                 "c": c[0::2] + 1j * c[1::2], "ado_n": n, "term_mode": tm}
+
+    def bath(self):
+        """(nu, c, c_bra) complex arrays of the exponential bath terms."""
+        return heom_model_bath(self)
 
 
 class State:
@@ -624,6 +631,14 @@ def heom_batch_response_2d(batch: Batch, rho_eqs, grid, precision="fp32"):
 
 def heom_model_set_graph_steps(model, steps):
     _check(_lib.heom_model_set_graph_steps(model.handle, int(steps)))
+
+
+def heom_model_bath(model):
+    """Rates nu_j, coefficients c_j and bra-side coefficients of the bath terms."""
+    M = model.n_terms
+    out = [np.zeros(2 * M) for _ in range(3)]
+    _check(_lib.heom_model_bath(model.handle, *[_ptr(a) for a in out]))
+    return tuple(a[0::2] + 1j * a[1::2] for a in out)
 
 
 def heom_model_set_kernel(model, precision, kernel):

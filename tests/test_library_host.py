@@ -78,6 +78,41 @@ def test_host_builder_matsubara_and_high_pade_order():
     np.testing.assert_allclose(ops["nu"], om.build(params).nu, rtol=1e-14)
 
 
+@pytest.mark.parametrize("case", ["underdamped", "overdamped", "matsubara", "cfg3"])
+def test_host_builder_brownian_baths_match_oracle(case):
+    # closed-form pole pair in C++ against the oracle's residues of J
+    if case == "cfg3":
+        params = w.cfg3_brownian(depth=2)[0]
+    else:
+        params = w.cfg2()[0]
+        params["depth"] = 3
+        wb = {"underdamped": [1.5, 0.7], "overdamped": [0.4, 0.3], "matsubara": [1.5, 0.7]}[case]
+        params = w.with_brownian_baths(params, wb, gamma=1.2 if case == "overdamped" else None)
+        if case == "matsubara":
+            params["decomp"] = "matsubara"
+    m = P.heom_model_build_host(params)
+    o = om.build(params)
+    nu, c, cb = m.bath()
+    assert (m.n_terms, m.n_ado) == (len(o.nu), len(o.hier))
+    np.testing.assert_allclose(nu, o.nu, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(c, o.c, rtol=1e-11, atol=1e-17)
+    np.testing.assert_allclose(cb, o.c_bra, rtol=1e-11, atol=1e-17)
+    ops = m.operators()
+    np.testing.assert_allclose(ops["nu"], np.real(o.nu), rtol=1e-13, atol=1e-15)
+    assert np.array_equal(ops["ado_n"], o.hier.n)
+    assert np.array_equal(ops["term_mode"], o.term_mode)
+    np.testing.assert_allclose(ops["H"], o.H, atol=1e-13)
+    if case != "overdamped":
+        assert np.any(np.imag(nu) != 0)
+
+
+def test_drude_bath_terms_are_real_rates():
+    m = P.heom_model_build_host(w.cfg2()[0])
+    nu, c, cb = m.bath()
+    assert np.all(np.imag(nu) == 0)
+    np.testing.assert_array_equal(cb, np.conj(c))
+
+
 def _bad(mutate):
     params, _ = w.cfg2()
     mutate(params)
@@ -105,7 +140,13 @@ def test_invalid_parameters_rejected():
         p["modes"][0]["n_keep"] = 12
         p["modes"][1]["n_keep"] = 12
 
-    for f in (keep_gt_basis, bad_coupling, pole, neg_dt, too_big):
+    def critical(p):
+        p["modes"][0]["omega_b"] = p["modes"][0]["gamma"] / 2
+
+    def neg_wb(p):
+        p["modes"][0]["omega_b"] = -1.0
+
+    for f in (keep_gt_basis, bad_coupling, pole, neg_dt, too_big, critical, neg_wb):
         assert _bad(f) == P.heom2dvs.HEOM_ERR_PARAM
 
 

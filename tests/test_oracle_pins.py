@@ -149,6 +149,22 @@ def test_brownian_correlation_matches_fdt_integral(gamma, wb):
     assert abs(np.sum(c12).imag) < 1e-15 * scale
 
 
+@pytest.mark.parametrize("decomp", ["pade", "matsubara"])
+@pytest.mark.parametrize("K", [1, 2, 4])
+def test_zero_frequency_sum_rule(decomp, K):
+    # int_0^inf Re C(t) dt = (pi/beta) J'(0) for any coth decomposition with
+    # the exact 2/x pole: sum_j Re(c_j/nu_j) must reproduce zeta/beta (Drude)
+    # and zeta gamma^2/(beta wb^2) (Brownian); the imaginary parts integrate
+    # to -int J(w)/w dw = -Lambda.
+    z, g, b, wb = 0.1, 0.2, 10.0, 0.7
+    nu, c = bath.drude_terms(z, g, b, K, decomp)
+    assert np.sum(c / nu).real == pytest.approx(z / b, rel=1e-12)
+    assert np.sum(c / nu).imag == pytest.approx(-z * g / 2, rel=1e-12)
+    nu, c = bath.brownian_terms(z, g, wb, b, K, decomp)
+    assert np.sum(c / nu).real == pytest.approx(z * g * g / (b * wb * wb), rel=1e-12)
+    assert np.sum(c / nu).imag == pytest.approx(-z * g / 2, rel=1e-12)
+
+
 def test_bra_coefficients_pairing():
     nu, c = bath.brownian_terms(0.1, 0.2, 1.0, 10.0, 2)
     cb = bath.bra_coefficients(nu, c)

@@ -10,6 +10,7 @@ from .configs import (  # noqa: F401
     cfg1,
     cfg2,
     cfg3,
+    cfg3_brownian,
     cfg4_instances,
     cfg5,
     cfg5_small,
@@ -20,5 +21,6 @@ from .configs import (  # noqa: F401
     paper_scale,
     fs_to_steps,
     response_grid,
+    with_brownian_baths,
 )
 from .states import random_hierarchy  # noqa: F401

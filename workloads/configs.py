@@ -174,6 +174,28 @@ def harmonic_pin(omega=1.0, zeta=0.1, gamma=0.2, V1=1.0, beta=10.0, K=2,
             "decomp": decomp, "dt": dt}
 
 
+def with_brownian_baths(params, omega_b=0.25, gamma=None):
+    """Copy of params whose baths are Brownian (underdamped-oscillator)
+    spectral densities of frequency omega_b (one value or one per mode)
+    instead of Drude ones; zeta, K and the decomposition are kept, gamma
+    optionally replaced.  Each mode then has K + 2 exponential terms."""
+    import copy
+    p = copy.deepcopy(params)
+    wb = list(omega_b) if isinstance(omega_b, (list, tuple)) else [omega_b] * len(p["modes"])
+    for m, x in zip(p["modes"], wb):
+        m["omega_b"] = float(x)
+        if gamma is not None:
+            m["gamma"] = float(gamma)
+    return p
+
+
+def cfg3_brownian(seed: int = 0, depth: int = 5):
+    """cfg3's three modes with Brownian baths (omega_b = 0.25, gamma = 0.2,
+    K = 2 Pade): 12 exponential terms, 6188 ADOs of 80 x 80 at depth 5."""
+    params, grid = cfg3(seed, depth=depth)
+    return with_brownian_baths(params, 0.25), grid
+
+
 def theta_size(params) -> int:
     """Number of fitted factors: g3 and g4 per mode, then bilinear and Fermi
     coupling scales, then common V1, V2, zeta and gamma scales."""
