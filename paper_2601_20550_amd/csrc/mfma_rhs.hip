@@ -139,12 +139,29 @@ __device__ inline void vset(typename Vec<T, VW>::type& v, int i, T x) {
   }
 }
 
-// Waves per row block: two for 4 <= NB <= 6 (the accumulators and neighbour
-// registers of a wave then fit three waves per SIMD, so a 2 NB-wave
-// workgroup spreads over the four SIMDs), one otherwise.
+// Launch shape per size class (measured on MI355X):
+//  * FP32, NB = 5 (d = 65..80): one wave per row block with the neighbour
+//    sums X_s accumulated in LDS, at most 128 VGPRs: two 5-wave workgroups
+//    (2 x 79 KB of LDS) share a CU and overlap their phases.
+//  * otherwise two waves per row block for 4 <= NB <= 6 (accumulators and
+//    neighbour registers of a wave fit three waves per SIMD, so a 2 NB-wave
+//    workgroup spreads over the four SIMDs), one below.
+//  * FP64 always accumulates X_s in LDS (its register form spills).
 template <typename T, int NB>
 constexpr int wpr_of() {
+  if (sizeof(T) == 4 && NB == 5) return 1;
   return (NB >= 4 && NB <= 6) ? 2 : 1;
+}
+template <typename T, int NB>
+constexpr bool x_in_lds() {
+  return sizeof(T) == 8 || NB == 5;
+}
+// minimum waves per SIMD requested from the register allocator
+template <typename T, int NB>
+constexpr int minw_of() {
+  if (wpr_of<T, NB>() == 2) return 3;
+  if (sizeof(T) == 4) return x_in_lds<T, NB>() ? 4 : 2;
+  return 1;
 }
 
 // Stages H (zero padded to DP x DP), the single-mode operators v_s and zero
@@ -274,8 +291,9 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
 
   // ---- couplings to the hierarchy neighbours ----------------------------
   // Each wave forms X_s (and Y_s) for its slab rows from 16-byte neighbour
-  // loads: in registers, staged once per mode in the LDS planes (FP32), or
-  // accumulated directly in the LDS planes (FP64, whose register form spills).
+  // loads: in registers, staged once per mode in the LDS planes, or
+  // accumulated directly in the LDS planes (x_in_lds: FP64, whose register
+  // form spills, and the FP32 shape that runs two workgroups per CU).
 #pragma unroll 1
   for (int s = 0; s < 4; ++s) {
     if (s >= sh.nm()) break;
@@ -285,7 +303,7 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
     const int ds = sh.dim(s), st = sh.stride(s);
     const T* vs = sV + s * 64;
     bool have_w = false;
-    if constexpr (sizeof(T) == 8) {
+    if constexpr (x_in_lds<T, NB>()) {
       __syncthreads();  // every wave is done with the previous LDS content
       for (int q = p0; q < p1; ++q) {
         const T* rm = in + traj_base + static_cast<long long>(op.nb_idx[q]) * 2 * dd + srow0 * d;
@@ -404,7 +422,7 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
       }
       __syncthreads();
     }
-    if constexpr (sizeof(T) == 8) {
+    if constexpr (x_in_lds<T, NB>()) {
       // left product: (V_s X_s)[a][c] = sum_k v_s[a_s][k] X_s[a + (k - a_s) st][c];  L += -i V X
       {
         int as[4], r0[4];
@@ -484,14 +502,18 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
 
   // ---- epilogue: out = y + coef * L ---------------------------------------
   // transpose the accumulators through LDS so that y and out move in
-  // 16-byte vectors (slab rows)
+  // 16-byte vectors (slab rows).  Only the d x d block is written: the
+  // padding rows and columns of the planes must stay zero (the matrix-core
+  // products multiply them by the zero padding of H, and the accumulators
+  // there hold contraction and damping terms of padding entries that would
+  // otherwise feed back and grow from one matrix to the next).
   __syncthreads();
 #pragma unroll
   for (int jj = 0; jj < JT; ++jj)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int a = rows0 + M::crow(lq, r), c = 16 * (j0 + jj) + lr;
-      if (j0 + jj < NB) {
+      if (j0 + jj < NB && a < d && c < d) {
         sRe[a * LD + c] = Rre[jj][r];
         sIm[a * LD + c] = Rim[jj][r];
       }
@@ -599,7 +621,7 @@ template <typename T, int NB, typename Shape, int VW>
 void launch_shape_vw(const DevOps<T>& op, const T* Hp, const T* in, const T* y, T* out, T coef, long long n_items,
                      int wg_per_cu, hipStream_t stream) {
   const size_t lds = Lds<T, NB>::bytes;
-  constexpr int MINW = (wpr_of<T, NB>() == 2) ? 3 : ((sizeof(T) == 4) ? 2 : 1);
+  constexpr int MINW = minw_of<T, NB>();
   auto kern = &rhs_mfma_kernel<T, NB, Shape, MINW, VW>;
   static bool configured = false;
   if (!configured) {
@@ -689,7 +711,7 @@ namespace {
 template <typename T, int NB, int VW>
 void launch_multi_nb(const InstDesc<T>* desc, int n_inst, T coef, long long n_items, hipStream_t stream) {
   const size_t lds = Lds<T, NB>::bytes;
-  constexpr int MINW = (wpr_of<T, NB>() == 2) ? 3 : ((sizeof(T) == 4) ? 2 : 1);
+  constexpr int MINW = minw_of<T, NB>();
   auto kern = &rhs_mfma_multi_kernel<T, NB, MINW, VW>;
   static bool configured = false;
   if (!configured) {

@@ -75,6 +75,31 @@ def test_rhs_parity(which, depth, adjoint, prec, kernel):
     assert _relerr(got, ref) < tol
 
 
+@pytest.mark.parametrize("which,B", [("cfg1", 16384), ("cfg2", 2048)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_padded_matrices_many_per_workgroup(which, B, prec, tol):
+    # d = 6 and 25 are padded to 16 and 32 in the LDS planes, and every
+    # persistent workgroup processes hundreds of matrices: padding entries left
+    # non-zero by one matrix must not reach the next (regression: they grew
+    # from matrix to matrix until 0 * inf poisoned the matrix-core products)
+    params = _params(which)
+    o = om.build(params)
+    m = P.heom_model_build(params)
+    P.heom_model_set_kernel(m, prec, "mfma")
+    s = P.State(m, B, prec)
+    s.set_ground()
+    x = w.random_hierarchy(3, len(o.hier), o.d, seed=9, hermitian=True, scale_by_depth=_depth_scale(o))
+    picks = [0, B // 2 + 1, B - 1]
+    for i, b in enumerate(picks):
+        s.upload_range(b, x[i:i + 1])
+    P.heom_propagate(m, s, 3)  # raises HEOM_ERR_UNSTABLE on a non-finite hierarchy
+    ref = oh.propagate(o, x, 3)
+    for i, b in enumerate(picks):
+        assert _relerr(s.download_range(b, 1)[0], ref[i]) < tol
+    g = oh.propagate(o, oh.ground_state_hierarchy(o), 3)
+    assert _relerr(s.download_range(1, 1)[0], g) < tol
+
+
 def test_rhs_parity_full_depth_three_modes():
     params = _params("cfg3")
     o = om.build(params)
