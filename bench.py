@@ -170,6 +170,9 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--depth", type=int, default=6)
     ap.add_argument("--spectrum", type=int, default=1, help="also time one full 2D spectrum")
+    ap.add_argument("--spectrum-t2", type=int, default=1,
+                    help="number of the workload's t2 values in the timed response call "
+                         "(1: t2 = 0 only; cfg3 has 0, 50, 100, 200 fs)")
     ap.add_argument("--eq-tol", type=float, default=1e-8)
     ap.add_argument("--eq-seconds", type=float, default=60.0)
     ap.add_argument("--cpu-baseline", type=int, default=1)
@@ -296,6 +299,25 @@ def main():
         line["s_per_2d_spectrum"] = time.perf_counter() - t0
         line["spectrum_config"] = {"t2": 0, "grid": [g1["n1"], g1["n3"]], "method": "adjoint",
                                    "finite": bool(np.isfinite(S).all())}
+        if args.spectrum_t2 > 1:
+            # several t2 values in one call: the t2 branches are propagated
+            # incrementally (progress on stderr)
+            g2 = dict(grid)
+            g2["t2_steps"] = list(grid["t2_steps"][:args.spectrum_t2])
+            P.heom_model_set_progress(
+                m, lambda ph, done, tot: print(f"{ph}: {done}/{tot} RK4 steps", file=sys.stderr, flush=True),
+                50)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            R = P.heom_response_2d(m, rho, g2, args.precision, "adjoint")
+            S = [P.heom_spectrum_2d(R[q, 0], R[q, 1], grid["steps_per_sample"] * params["dt"])
+                 for q in range(R.shape[0])]
+            torch.cuda.synchronize()
+            P.heom_model_set_progress(m, None)
+            dt_fs = params["dt"] * w.FS_PER_TIME_UNIT
+            line["s_2d_spectra_t2_set"] = {
+                "t2_fs": [round(x * dt_fs, 1) for x in g2["t2_steps"]], "s": time.perf_counter() - t0,
+                "finite": bool(all(np.isfinite(x).all() for x in S))}
         line["equilibration"] = {"method": "GMRES on I - Phi^500 (FP64)", "s": t_eq,
                                  "rk4_steps": 100 + 500 * eq_applies, "residual": eq_res,
                                  "tol": args.eq_tol}

@@ -156,6 +156,10 @@ struct heom_model {
   };
   int graph_steps = 0;
   hipStream_t cap_stream = nullptr;
+  // progress reporting of long response calls (off when fn is null)
+  heom_progress_fn progress_fn = nullptr;
+  void* progress_ctx = nullptr;
+  int progress_every = 0;
   std::vector<Graph> graphs;
   void clear_graphs() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
@@ -444,6 +448,40 @@ void rk4_steps_scratch(heom_model* m, T* y, int n_traj, int n_steps, bool adjoin
   rk4_steps<T>(m, y, w1, w2, n_traj, n_steps, adjoint);
 }
 
+// Progress of one phase of a response call: steps counted over all its
+// trajectory batches and pathways.
+struct Progress {
+  heom_model* m;
+  const char* phase;
+  long long total, done = 0, next = 0;
+  Progress(heom_model* mm, const char* ph, long long tot) : m(mm), phase(ph), total(tot) {
+    next = m->progress_every;
+  }
+  bool on() const { return m->progress_fn && m->progress_every > 0; }
+};
+
+// rk4_steps, split at every multiple of the progress interval (counted over
+// the whole phase) to synchronise and report there.
+template <typename T>
+void rk4_steps_reported(heom_model* m, T* y, T* w1, T* w2, int n_traj, int n_steps, Progress& pr) {
+  if (!pr.on()) {
+    rk4_steps<T>(m, y, w1, w2, n_traj, n_steps, false);
+    pr.done += n_steps;
+    return;
+  }
+  while (n_steps > 0) {
+    const int k = static_cast<int>(std::min<long long>(n_steps, pr.next - pr.done));
+    rk4_steps<T>(m, y, w1, w2, n_traj, k, false);
+    n_steps -= k;
+    pr.done += k;
+    if (pr.done >= pr.next) {
+      hip_check(hipStreamSynchronize(m->stream), "sync");
+      m->progress_fn(pr.phase, pr.done, pr.total, m->progress_ctx);
+      pr.next += m->progress_every;
+    }
+  }
+}
+
 template <typename T>
 double absmax(heom_model* m, const T* x, long long n_mats) {
   if (m->red_partial.bytes < static_cast<size_t>(n_mats) * sizeof(double)) {
@@ -573,6 +611,9 @@ void response_direct(heom_model* m, const heom_state* rho_eq, const heom_grid& g
   DevBuf snap(tb * n1);
   const int C = auto_batch(m, n1, sizeof(T), 3, 0, max_batch);
   DevBuf Z(tb * C), W1(tb * C), W2(tb * C);
+  const long long n_batches = (n1 + C - 1) / C;
+  Progress pr(m, "t2/t3 propagation",
+              n_pw * n_batches * (g.t2_steps[g.n_t2 - 1] + static_cast<long long>(g.n_t2) * (n3 - 1) * sps));
   for (int P = 0; P < n_pw; ++P) {
     const int* pw = ops + 3 * P;
     t1_snapshots<T>(m, rho_eq, pw[0], pw[1], n1, sps, snap.as<T>());
@@ -581,12 +622,12 @@ void response_direct(heom_model* m, const heom_state* rho_eq, const heom_grid& g
       T* Y = snap.as<T>() + j0 * te;
       int done = 0;
       for (int i = 0; i < g.n_t2; ++i) {
-        rk4_steps<T>(m, Y, W1.as<T>(), W2.as<T>(), c, g.t2_steps[i] - done, false);
+        rk4_steps_reported<T>(m, Y, W1.as<T>(), W2.as<T>(), c, g.t2_steps[i] - done, pr);
         done = g.t2_steps[i];
         heom::launch_commutator<T>(m->mu64[pw[2]].as<double>(), 0, Y, Z.as<T>(), d,
                                    static_cast<long long>(c) * m->hm.n_ado, m->stream);
         for (int k = 0; k < n3; ++k) {
-          if (k) rk4_steps<T>(m, Z.as<T>(), W1.as<T>(), W2.as<T>(), c, sps, false);
+          if (k) rk4_steps_reported<T>(m, Z.as<T>(), W1.as<T>(), W2.as<T>(), c, sps, pr);
           double* out = Rdev + 2 * ((((static_cast<long long>(i) * n_pw + P) * n1 + j0) * n3) + k);
           heom::launch_trace<T>(m->mu64[HEOM_OP_MU].as<double>(), Z.as<T>(), d, te, c, out, n3, m->stream);
         }
@@ -632,6 +673,7 @@ void response_adjoint(heom_model* m, const heom_state* rho_eq, const heom_grid& 
   DevBuf W1(tb * C), W2(tb * C);
   DevBuf work(heom::pair_work_doubles(C, n3, m->hm.n_ado, d) * sizeof(double));
   int psi_op = one_d3 ? ops[2] : -1;
+  Progress pr(m, "t2 propagation", static_cast<long long>(n_pw) * ((n1 + C - 1) / C) * g.t2_steps[g.n_t2 - 1]);
   for (int P = 0; P < n_pw; ++P) {
     const int* pw = ops + 3 * P;
     if (pw[2] != psi_op) {
@@ -645,7 +687,7 @@ void response_adjoint(heom_model* m, const heom_state* rho_eq, const heom_grid& 
       T* Y = snap.as<T>() + j0 * te;
       int done = 0;
       for (int i = 0; i < g.n_t2; ++i) {
-        rk4_steps<T>(m, Y, W1.as<T>(), W2.as<T>(), c, g.t2_steps[i] - done, false);
+        rk4_steps_reported<T>(m, Y, W1.as<T>(), W2.as<T>(), c, g.t2_steps[i] - done, pr);
         done = g.t2_steps[i];
         double* out = Rdev + 2 * (((static_cast<long long>(i) * n_pw + P) * n1 + j0) * n3);
         // R = i^3 <Psi_k, Y_j> = -i <.,.>
@@ -2138,6 +2180,15 @@ int heom_model_set_kernel(heom_model* m, int precision, int kernel) {
     if (kernel != HEOM_KERNEL_GENERIC && !ok) throw HeomError(HEOM_ERR_PARAM, "matrix-core kernel unsupported for this d");
     m->kernel[precision] = kernel;
     m->clear_graphs();
+  });
+}
+
+int heom_model_set_progress(heom_model* m, heom_progress_fn fn, void* ctx, int every_steps) {
+  return guarded([&] {
+    if (!m) throw HeomError(HEOM_ERR_PARAM, "null model");
+    m->progress_fn = every_steps > 0 ? fn : nullptr;
+    m->progress_ctx = ctx;
+    m->progress_every = fn ? every_steps : 0;
   });
 }
 

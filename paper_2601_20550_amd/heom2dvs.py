@@ -82,6 +82,7 @@ class heom_op_grad(C.Structure):
 
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_PROGRESS_FN = C.CFUNCTYPE(None, C.c_char_p, C.c_longlong, C.c_longlong, C.c_void_p)
 _FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 # name -> (restype, argtypes)
@@ -138,6 +139,7 @@ _SIGS = {
                                          C.c_void_p]),
     "heom_model_set_kernel": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "heom_model_set_graph_steps": (C.c_int, [C.c_void_p, C.c_int]),
+    "heom_model_set_progress": (C.c_int, [C.c_void_p, _PROGRESS_FN, C.c_void_p, C.c_int]),
     "heom_model_get_kernel": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
     "heom_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int),
                                 C.c_void_p]),
@@ -639,6 +641,19 @@ def heom_model_bath(model):
     out = [np.zeros(2 * M) for _ in range(3)]
     _check(_lib.heom_model_bath(model.handle, *[_ptr(a) for a in out]))
     return tuple(a[0::2] + 1j * a[1::2] for a in out)
+
+
+def heom_model_set_progress(model, fn, every_steps=50):
+    """Call fn(phase, done, total) every `every_steps` RK4 steps of the batched
+    t2 / t3 propagations of later response calls on this model; fn=None turns
+    it off."""
+    if fn is None:
+        model._progress_cb = None
+        _check(_lib.heom_model_set_progress(model.handle, _PROGRESS_FN(), None, 0))
+        return
+    cb = _PROGRESS_FN(lambda phase, done, total, ctx: fn(phase.decode(), int(done), int(total)))
+    model._progress_cb = cb  # keep the thunk alive while the library holds it
+    _check(_lib.heom_model_set_progress(model.handle, cb, None, int(every_steps)))
 
 
 def heom_model_set_kernel(model, precision, kernel):

@@ -497,3 +497,21 @@ def test_empty_and_zero_work_requests():
     with pytest.raises(P.heom2dvs.HeomError) as e:
         P.heom_propagate(m, s, -1)
     assert e.value.code == P.heom2dvs.HEOM_ERR_PARAM
+
+
+@pytest.mark.parametrize("method", ["direct", "adjoint"])
+def test_progress_reports_do_not_change_results(method):
+    m, rho, grid, ref = _response_case("cfg2", 2, 4, 5, [0, 12], None)
+    plain = P.heom_response_2d(m, rho, grid, "fp64", method)
+    calls = []
+    P.heom_model_set_progress(m, lambda ph, done, tot: calls.append((ph, done, tot)), 7)
+    got = P.heom_response_2d(m, rho, grid, "fp64", method, max_batch=3)
+    P.heom_model_set_progress(m, None)
+    np.testing.assert_array_equal(got, P.heom_response_2d(m, rho, grid, "fp64", method, max_batch=3))
+    assert _relerr(got, plain) < 1e-13 and _relerr(got, ref) < 1e-10
+    # 2 pathways x 2 batches (4 t1 samples, 3 per batch) x steps per batch
+    per_batch = 12 + (2 * 3 * 5 if method == "direct" else 0)
+    total = 2 * 2 * per_batch
+    assert calls and all(t == total for _, _, t in calls)
+    done = [d for _, d, _ in calls]
+    assert done == sorted(done) and all(x % 7 == 0 for x in done) and total - done[-1] < 7
