@@ -101,6 +101,12 @@ typedef struct {
   int depth;                        /* hierarchy depth L                     */
   int decomp;                       /* heom_decomp                           */
   double dt;                        /* RK4 step (1/omega0)                   */
+  /* Optional non-triangular filter (0 = off): keep only the ADOs whose
+   * total damping rate sum_j n_j Re(nu_j) is at most rate_cut (relative
+   * tolerance 1e-9), in addition to |n| <= depth.  The paper's own filter is
+   * not stated; this rate rule keeps the set closed under n -> n - e_j (all
+   * Re nu_j > 0), as the truncation of Eq. HEOM_DB requires. */
+  double rate_cut;
 } heom_params;
 
 typedef struct {

@@ -5,7 +5,9 @@ non-negative integer per exponential bath term, n = (n_j), j running over the
 (mode s, term k) pairs; an index with a negative entry denotes the zero
 operator and n +- e_j increments/decrements entry j.  The paper does not state
 its truncation; the triangular set |n| = sum_j n_j <= L is used, ordered by
-depth |n| and then ascending lexicographically within a depth.
+depth |n| and then ascending lexicographically within a depth.  Optionally the
+set is filtered further by the total damping rate, sum_j n_j Re(nu_j) <= cut
+(relative tolerance 1e-9), which keeps it closed under n -> n - e_j.
 """
 
 from __future__ import annotations
@@ -32,10 +34,14 @@ class Hierarchy:
     down[i, j] = index of n_i - e_j, or -1 when n_ij = 0.
     """
 
-    def __init__(self, n_terms: int, depth: int):
+    def __init__(self, n_terms: int, depth: int, rates=None, rate_cut: float = 0.0):
         self.n_terms = n_terms
         self.depth = depth
         self.ados = enumerate_ados(n_terms, depth)
+        if rate_cut > 0.0:
+            r = np.asarray(rates, dtype=float)
+            self.ados = [n for n in self.ados
+                         if sum(k * x for k, x in zip(n, r)) <= rate_cut * (1.0 + 1e-9)]
         self.index = {n: i for i, n in enumerate(self.ados)}
         N = len(self.ados)
         self.n = np.array(self.ados, dtype=np.int64).reshape(N, n_terms)

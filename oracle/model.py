@@ -139,7 +139,7 @@ class Model:
         return np.conj(self.c) if self.cb is None else self.cb
 
 
-def make_model(H, V, mu, term_mode, nu, c, depth, dt=0.01, dims=None, modes=None, cb=None):
+def make_model(H, V, mu, term_mode, nu, c, depth, dt=0.01, dims=None, modes=None, cb=None, rate_cut=0.0):
     """Assemble a Model from explicit operators (used by engine-level checks).
 
     Complex rates nu_j (Brownian baths) need the bra-side coefficients cb;
@@ -152,7 +152,7 @@ def make_model(H, V, mu, term_mode, nu, c, depth, dt=0.01, dims=None, modes=None
     N = quanta(dims)
     mu = np.asarray(mu, dtype=float)
     mu_plus = np.where(N[:, None] > N[None, :], mu, 0.0)
-    hier = Hierarchy(len(nu), depth)
+    hier = Hierarchy(len(nu), depth, np.real(np.asarray(nu, dtype=complex)), rate_cut)
     nu = np.asarray(nu, dtype=complex)
     c = np.asarray(c, dtype=complex)
     if np.all(nu.imag == 0):
@@ -218,4 +218,5 @@ def build_from_modes(params, modes) -> Model:
         nus += list(nu)
         cs += list(c)
     return make_model(H, V, mu, term_mode, nus, cs, int(params["depth"]),
-                      dt=float(params["dt"]), dims=dims, modes=modes)
+                      dt=float(params["dt"]), dims=dims, modes=modes,
+                      rate_cut=float(params.get("rate_cut", 0.0)))

@@ -385,6 +385,17 @@ HostModel build_host_model(const heom_params& p) {
       enumerate_level(M, level, cur, 0, ados);
     }
   }
+  if (p.rate_cut < 0.0 || !std::isfinite(p.rate_cut)) throw std::invalid_argument("rate_cut must be >= 0");
+  if (p.rate_cut > 0.0) {
+    // rate filter: sum_j n_j Re nu_j <= rate_cut (closed under n -> n - e_j)
+    std::vector<std::vector<int>> kept;
+    for (auto& n : ados) {
+      double r = 0.0;
+      for (int j = 0; j < M; ++j) r += n[j] * hm.nu[j];
+      if (r <= p.rate_cut * (1.0 + 1e-9)) kept.push_back(std::move(n));
+    }
+    ados.swap(kept);
+  }
   if (ados.size() > 2000000) throw std::invalid_argument("hierarchy larger than 2e6 ADOs");
   hm.n_ado = static_cast<int>(ados.size());
   std::map<std::string, int> index;

@@ -62,7 +62,7 @@ class heom_params(C.Structure):
     _fields_ = [("n_modes", C.c_int), ("modes", C.POINTER(heom_mode)),
                 ("n_couplings", C.c_int), ("couplings", C.POINTER(heom_coupling)),
                 ("beta", C.c_double), ("depth", C.c_int), ("decomp", C.c_int),
-                ("dt", C.c_double)]
+                ("dt", C.c_double), ("rate_cut", C.c_double)]
 
 
 class heom_info(C.Structure):
@@ -207,6 +207,7 @@ def _params_struct(params):
     p.depth = int(params["depth"])
     p.decomp = HEOM_MATSUBARA if params.get("decomp", "pade") == "matsubara" else HEOM_PADE
     p.dt = float(params["dt"])
+    p.rate_cut = float(params.get("rate_cut", 0.0))
     return p, (arr, carr)
 
 

@@ -515,3 +515,37 @@ def test_progress_reports_do_not_change_results(method):
     assert calls and all(t == total for _, _, t in calls)
     done = [d for _, d, _ in calls]
     assert done == sorted(done) and all(x % 7 == 0 for x in done) and total - done[-1] < 7
+
+
+@pytest.mark.parametrize("which,depth,cut", [("cfg2", 4, 2.0), ("cfg3", 3, 2.0)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_rhs_parity_rate_filtered_hierarchy(which, depth, cut, prec, kernel):
+    # non-triangular index set: neighbours outside the kept set are absent
+    params = _params(which, depth, rate_cut=cut)
+    o = om.build(params)
+    assert len(o.hier) < len(om.build(_params(which, depth)).hier)
+    m = P.heom_model_build(params)
+    assert m.n_ado == len(o.hier)
+    P.heom_model_set_kernel(m, prec, kernel)
+    x = w.random_hierarchy(2, len(o.hier), o.d, seed=21, scale_by_depth=_depth_scale(o))
+    xin = P.State(m, 2, prec)
+    xout = P.State(m, 2, prec)
+    xin.upload(x)
+    for adjoint in (False, True):
+        P.heom_rhs(m, xin, xout, adjoint)
+        assert _relerr(xout.download(), oh.rhs(o, x, adjoint=adjoint)) < (1e-12 if prec == "fp64" else 2e-6)
+
+
+@pytest.mark.parametrize("method", ["direct", "adjoint"])
+def test_response_2d_parity_rate_filtered(method):
+    params = _params("cfg2", 3, rate_cut=1.5)
+    o = om.build(params)
+    m = P.heom_model_build(params)
+    rho_ref = oh.propagate(o, oh.ground_state_hierarchy(o), 50)
+    rho = P.State(m, 1, "fp64")
+    rho.upload(rho_ref[None])
+    grid = {"n1": 5, "n3": 5, "steps_per_sample": 5, "t2_steps": [0, 10]}
+    ref = oh.response_2d(o, rho_ref, grid)
+    assert _relerr(P.heom_response_2d(m, rho, grid, "fp64", method), ref) < 1e-10
+    assert _relerr(P.heom_response_2d(m, rho, grid, "fp32", method), ref) < 1e-4

@@ -106,6 +106,17 @@ def test_host_builder_brownian_baths_match_oracle(case):
         assert np.any(np.imag(nu) != 0)
 
 
+@pytest.mark.parametrize("which,cut", [("cfg2", 0.9), ("cfg3", 1.5), ("cfg3b", 1.0)])
+def test_host_builder_rate_filter_matches_oracle(which, cut):
+    params = w.cfg3_brownian(depth=4)[0] if which == "cfg3b" else getattr(w, which)()[0]
+    params["depth"] = min(params["depth"], 4)
+    params["rate_cut"] = cut
+    m = P.heom_model_build_host(params)
+    o = om.build(params)
+    assert m.n_ado == len(o.hier) < len(om.build(dict(params, rate_cut=0.0)).hier)
+    assert np.array_equal(m.operators()["ado_n"], o.hier.n)
+
+
 def test_drude_bath_terms_are_real_rates():
     m = P.heom_model_build_host(w.cfg2()[0])
     nu, c, cb = m.bath()
@@ -146,7 +157,10 @@ def test_invalid_parameters_rejected():
     def neg_wb(p):
         p["modes"][0]["omega_b"] = -1.0
 
-    for f in (keep_gt_basis, bad_coupling, pole, neg_dt, too_big, critical, neg_wb):
+    def neg_cut(p):
+        p["rate_cut"] = -1.0
+
+    for f in (keep_gt_basis, bad_coupling, pole, neg_dt, too_big, critical, neg_wb, neg_cut):
         assert _bad(f) == P.heom2dvs.HEOM_ERR_PARAM
 
 

@@ -5,6 +5,7 @@ textbook special case or a brute-force computation that does not reuse the
 piece under test.
 """
 
+import itertools
 import math
 
 import mpmath
@@ -208,6 +209,39 @@ def test_hierarchy_brute_force_small():
 
 
 # -------------------------------------------------------- single mode -------
+
+def test_rate_filtered_hierarchy_brute_force_and_closure():
+    rates = np.array([0.2, 0.63, 1.95, 0.1])
+    for cut in (0.5, 1.3, 2.0, 100.0):
+        h = hierarchy.Hierarchy(4, 4, rates, cut)
+        brute = [n for n in itertools.product(range(5), repeat=4)
+                 if sum(n) <= 4 and float(np.dot(n, rates)) <= cut * (1 + 1e-9)]
+        assert sorted(h.ados, key=lambda n: (sum(n), n)) == h.ados
+        assert set(h.ados) == set(brute)
+        for i, n in enumerate(h.ados):  # closed under n -> n - e_j
+            for j in range(4):
+                if n[j] > 0:
+                    assert h.down[i, j] >= 0
+    assert hierarchy.Hierarchy(4, 4, rates, 100.0).ados == hierarchy.Hierarchy(4, 4).ados
+
+
+def test_rate_filtered_rhs_is_restricted_full_rhs():
+    # truncating the index set means the removed ADOs are zero: the filtered
+    # generator equals P L P^T with P the restriction to the kept ADOs
+    p, _ = w.cfg2()
+    p["depth"] = 3
+    full = om.build(p)
+    p["rate_cut"] = 0.9
+    filt = om.build(p)
+    assert 0 < len(filt.hier) < len(full.hier)
+    keep = np.array([full.hier.index[n] for n in filt.hier.ados])
+    x = w.random_hierarchy(1, len(filt.hier), filt.d, seed=4)[0]
+    X = np.zeros((len(full.hier), full.d, full.d), dtype=complex)
+    X[keep] = x
+    np.testing.assert_allclose(heom.rhs(filt, x), heom.rhs(full, X)[keep], atol=1e-14)
+    np.testing.assert_allclose(heom.rhs(filt, x, adjoint=True), heom.rhs(full, X, adjoint=True)[keep],
+                               atol=1e-14)
+
 
 def test_harmonic_mode_ladder():
     mode = dict(omega=1.3, g3=0.0, g4=0.0, V1=1.0, V2=0.0, zeta=0.0, gamma=0.2,

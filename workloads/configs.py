@@ -10,7 +10,8 @@ Parameter dictionary layout (both the oracle and the C-ABI binding read it):
     {"modes": [{"omega", "g3", "g4", "V1", "V2", "zeta", "gamma",
                 "mu1", "mu2", "n_basis", "n_keep", "K"}, ...],
      "couplings": [{"s", "t", "g_st", "g_s2t", "g_st2", "mu_st"}, ...],
-     "beta", "depth", "decomp" ("pade" | "matsubara"), "dt"}
+     "beta", "depth", "decomp" ("pade" | "matsubara"), "dt",
+     optional "rate_cut" (hierarchy filter; modes may add "omega_b")}
 
 Mode keys follow the model of Sec. II.A: the potential
 omega*q^2/2 + g3 q^3/3! + g4 q^4/4! (Eq. Potentials plus an optional quartic
