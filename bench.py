@@ -30,8 +30,11 @@ sys.path.insert(0, ROOT)
 # rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs (profiles/rhs_mfma_kernel_3mode_L6_b128_fp32.md),
 # scaled by the counters' readings for kernels of known size.  Keyed by the
 # kernel source hash: a changed kernel reports traffic null until re-profiled.
-PROFILED_TRAFFIC = {
-    "b53a0fd195dabf58": {"read_GB": 332.0, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
+PROFILED_TRAFFIC = {  # source hash -> kernel choice -> bytes per launch
+    "b53a0fd195dabf58": {
+        "mfma": {"read_GB": 332.0, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
+        "mfma_dyn": {"read_GB": 327.1, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
+    },
 }
 
 PEAKS = {  # MI355X published dense peaks
@@ -263,8 +266,8 @@ def main():
         "autotune": tune,
     }
 
-    prof = PROFILED_TRAFFIC.get(kernel_source_hash())
-    if (prof and kernel.startswith("mfma") and prof["batch"] == B
+    prof = PROFILED_TRAFFIC.get(kernel_source_hash(), {}).get(kernel)
+    if (prof and prof["batch"] == B
             and prof["precision"] == args.precision and args.depth == 6 and args.workload == "cfg3"):
         line["roofline"]["traffic"] = (prof["read_GB"] + prof["write_GB"]) * 1e9
         line["roofline"]["traffic_unit"] = "bytes per launch (HBM, calibrated rocprofv3 counters)"
