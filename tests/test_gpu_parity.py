@@ -135,27 +135,34 @@ def test_rk4_steps_parity(prec, tol, kernel):
     assert _relerr(s.download(), ref) < tol
 
 
-def test_full_size_batched_step_sampled():
-    """Three-mode depth-6 model, 128 trajectories (the benchmark batch):
-    one FP32 RK4 step on the whole batch; trajectories 0 (ground state) and
-    77 (random) are compared with the oracle."""
+@pytest.fixture(scope="module")
+def full_size_refs():
     params = _params("cfg3")
     o = om.build(params)
+    x = w.random_hierarchy(1, len(o.hier), o.d, seed=77, hermitian=True,
+                           scale_by_depth=_depth_scale(o))
+    g = np.zeros_like(x)
+    g[0, 0, 0, 0] = 1.0
+    return params, x, oh.rk4_step(o, x), oh.rk4_step(o, g)
+
+
+@pytest.mark.parametrize("kernel", ["mfma", "mfma_dyn"])
+def test_full_size_batched_step_sampled(full_size_refs, kernel):
+    """Three-mode depth-6 model, 128 trajectories (the benchmark batch) with
+    either matrix-core instantiation the benchmark's autotuner may choose:
+    one FP32 RK4 step on the whole batch; trajectories 0 (ground state) and
+    77 (random) are compared with the oracle."""
+    params, x, ref77, ref0 = full_size_refs
     m = P.heom_model_build(params)
+    P.heom_model_set_kernel(m, "fp32", kernel)
     B = 128
     s = P.State(m, B, "fp32")
     s.set_ground()
-    x = w.random_hierarchy(1, len(o.hier), o.d, seed=77, hermitian=True,
-                           scale_by_depth=_depth_scale(o))
     s.upload_range(77, x)
     P.heom_propagate(m, s, 1)
     got77 = s.download_range(77, 1)
     got0 = s.download_range(0, 1)
-    ref77 = oh.rk4_step(o, x)
     assert _relerr(got77, ref77) < 1e-5
-    g = np.zeros_like(x)
-    g[0, 0, 0, 0] = 1.0
-    ref0 = oh.rk4_step(o, g)
     assert _relerr(got0, ref0) < 1e-5
     # an untouched trajectory stays exactly the ground-state step
     got5 = s.download_range(5, 1)
