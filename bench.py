@@ -178,6 +178,8 @@ def main():
                          "(1: t2 = 0 only; cfg3 has 0, 50, 100, 200 fs)")
     ap.add_argument("--eq-tol", type=float, default=1e-8)
     ap.add_argument("--eq-seconds", type=float, default=60.0)
+    ap.add_argument("--eq-chunk", type=int, default=10,
+                    help="GMRES applications per refinement call (100 = one full restart cycle)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--multi", type=int, default=1,
                     help="1: also time the 64-instance uneven batch; 2: and one instance at a time")
@@ -275,21 +277,27 @@ def main():
 
     if args.spectrum:
         # rho_eq: 100 RK4 steps from |0><0|, then GMRES corrections in chunks of
-        # 10 applications of 500 steps until the residual reaches --eq-tol or
-        # --eq-seconds have passed (progress on stderr)
+        # --eq-chunk applications of 500 steps until the residual reaches
+        # --eq-tol or --eq-seconds have passed (progress on stderr)
         torch.cuda.synchronize()
         t_eq = time.perf_counter()
         rho = P.State(m, 1, "fp64")
         rho.set_ground()
         P.heom_propagate(m, rho, 100)
         eq_applies, eq_res = 0, float("inf")
+        if args.eq_chunk > 10:
+            P.heom_model_set_progress(
+                m, lambda ph, done, tot: print(f"{ph}: {done}/{tot} RK4 steps", file=sys.stderr, flush=True),
+                5000)
         while True:
-            a, eq_res = P.heom_stationary_refine(m, rho, tol=args.eq_tol, max_applies=10)
+            a, eq_res = P.heom_stationary_refine(m, rho, tol=args.eq_tol, max_applies=args.eq_chunk,
+                                                 restart=max(10, args.eq_chunk))
             eq_applies += a
             print(f"equilibration: {eq_applies} applications, residual {eq_res:.3e}", file=sys.stderr,
                   flush=True)
             if eq_res <= args.eq_tol or time.perf_counter() - t_eq > args.eq_seconds or a == 0:
                 break
+        P.heom_model_set_progress(m, None)
         torch.cuda.synchronize()
         t_eq = time.perf_counter() - t_eq
         g1 = dict(grid)

@@ -390,13 +390,17 @@ int heom_model_get_kernel(const heom_model* model, int precision, int* kernel_ou
  * model's stream.  Default 0.  Timing mode (heom_timing_enable) always
  * launches directly. */
 int heom_model_set_graph_steps(heom_model* model, int steps);
-/* Progress of long response calls: while set, the batched t2 (and, for the
- * direct method, t3) propagations of heom_response_2d /
- * heom_response_2d_pathways synchronise the model's stream every
- * `every_steps` RK4 steps and call fn(phase, steps_done, steps_total, ctx)
- * on the calling thread (steps counted over all trajectory batches and
- * pathways of the call).  fn = NULL or every_steps <= 0 turns it off
- * (default).  The callback must not call into this library. */
+/* Progress of long calls: while set, the batched t2 (and, for the direct
+ * method, t3) propagations of heom_response_2d / heom_response_2d_pathways
+ * ("t2 propagation", "t2/t3 propagation": steps counted over all trajectory
+ * batches and pathways of the call) and the GMRES operator applications of
+ * heom_equilibrate_krylov / heom_stationary_refine and of the stationary
+ * term of heom_response_2d_vjp ("stationary solve": steps of all
+ * applications, of at most max_applies x steps_per_apply) synchronise the
+ * model's stream every `every_steps` RK4 steps (at the next application
+ * boundary for the stationary solve) and call fn(phase, steps_done,
+ * steps_total, ctx) on the calling thread.  fn = NULL or every_steps <= 0
+ * turns it off (default).  The callback must not call into this library. */
 typedef void (*heom_progress_fn)(const char* phase, long long done, long long total, void* ctx);
 int heom_model_set_progress(heom_model* model, heom_progress_fn fn, void* ctx, int every_steps);
 /* Times every kernel variant on a scratch batch of n_traj trajectories in

@@ -926,6 +926,9 @@ struct Krylov {
   int msteps;
   long long te;
   DevBuf part, dot, tmp;
+  // progress reporting (heom_model_set_progress): RK4 steps of the operator
+  // applications so far, of at most steps_total
+  long long steps_done = 0, steps_total = 0, next_report = 0;
   Krylov(heom_model* mm, bool adj, int ms) : m(mm), adjoint(adj), msteps(ms), te(mm->traj_elems()) {
     part = DevBuf(static_cast<size_t>(2 * heom::hdot_parts()) * sizeof(double));
     dot = DevBuf(2 * sizeof(double));
@@ -952,6 +955,12 @@ struct Krylov {
     rk4_steps_scratch<double>(m, tmp.as<double>(), 1, msteps, adjoint);
     copy(v, w);
     axpy(-1.0, tmp.as<double>(), w);
+    steps_done += msteps;
+    if (m->progress_fn && m->progress_every > 0 && steps_done >= next_report) {
+      hip_check(hipStreamSynchronize(m->stream), "sync");
+      m->progress_fn("stationary solve", steps_done, steps_total, m->progress_ctx);
+      next_report = (steps_done / m->progress_every + 1) * m->progress_every;
+    }
   }
 };
 
@@ -1344,6 +1353,7 @@ void response_vjp(heom_model* m, const heom_state* rho_eq, const heom_grid& gr, 
     DevBuf kd(static_cast<size_t>(te) * sizeof(double)), bsum(static_cast<size_t>(te) * sizeof(double));
     {
       Krylov K(m, true, M);
+      K.steps_total = static_cast<long long>(std::max(1, max_steps / M)) * M;
       K.zero(bsum.as<double>());
       for (int n = 0; n < M; ++n) {
         if (n) rk4_steps_scratch<double>(m, grho.as<double>(), 1, 1, true);
@@ -1798,6 +1808,7 @@ void krylov_refine(heom_model* m, double* rho, double tol, int steps_per_apply, 
                    int* used_out, double* res_out) {
   const long long te = m->traj_elems();
   Krylov K(m, false, steps_per_apply);
+  K.steps_total = static_cast<long long>(max_applies) * steps_per_apply;
   DevBuf b(static_cast<size_t>(te) * sizeof(double)), x(static_cast<size_t>(te) * sizeof(double));
   int used = 0;
   double res = residual_of<double>(m, rho, 1);

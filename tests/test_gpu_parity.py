@@ -556,3 +556,21 @@ def test_response_2d_parity_rate_filtered(method):
     ref = oh.response_2d(o, rho_ref, grid)
     assert _relerr(P.heom_response_2d(m, rho, grid, "fp64", method), ref) < 1e-10
     assert _relerr(P.heom_response_2d(m, rho, grid, "fp32", method), ref) < 1e-4
+
+
+def test_progress_reports_in_stationary_solve():
+    params = _params("cfg1")
+    params["dt"] = 0.05
+    m = P.heom_model_build(params)
+    ref, ref_applies, ref_res = P.heom_equilibrate_krylov(m, tol=1e-11, steps_per_apply=200)
+    calls = []
+    P.heom_model_set_progress(m, lambda ph, done, tot: calls.append((ph, done, tot)), 300)
+    got, applies, res = P.heom_equilibrate_krylov(m, tol=1e-11, steps_per_apply=200)
+    P.heom_model_set_progress(m, None)
+    np.testing.assert_array_equal(got.download(), ref.download())
+    assert (applies, res) == (ref_applies, ref_res)
+    assert calls and all(ph == "stationary solve" for ph, _, _ in calls)
+    done = [d for _, d, _ in calls]
+    assert done == sorted(done) and all(x % 200 == 0 for x in done)
+    # one report per crossing of a multiple of 300 steps, at the next application boundary
+    assert len(done) == len({x // 300 for x in done})
