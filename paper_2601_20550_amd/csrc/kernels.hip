@@ -175,6 +175,74 @@ __global__ __launch_bounds__(256) void commutator_kernel(const double* __restric
   }
 }
 
+// Same operation with D and the matrix staged in LDS and 4 x 4 output blocks
+// per thread (FP64 arithmetic, the matrix kept in its storage type in LDS):
+// one block of ceil(d/4)^2 threads (rounded up to whole waves) per matrix.
+// Summation over k in the same order as commutator_kernel.
+template <typename T>
+__global__ __launch_bounds__(512) void commutator_tiled_kernel(const double* __restrict__ D, int transpose,
+                                                                const T* __restrict__ src, T* dst, int d) {
+  extern __shared__ unsigned char smem_raw[];
+  const int ld = d + 1;
+  double* sD = reinterpret_cast<double*>(smem_raw);
+  T* sXr = reinterpret_cast<T*>(sD + d * ld);
+  T* sXi = sXr + d * ld;
+  const int dd = d * d;
+  const long long base = static_cast<long long>(blockIdx.x) * 2 * dd;
+  for (int e = threadIdx.x; e < dd; e += blockDim.x) {
+    const int a = e / d, c = e - (e / d) * d;
+    sD[a * ld + c] = transpose ? D[c * d + a] : D[e];
+    sXr[a * ld + c] = src[base + e];
+    sXi[a * ld + c] = src[base + dd + e];
+  }
+  __syncthreads();
+  const int nt = (d + 3) / 4;
+  const int t = threadIdx.x;
+  if (t >= nt * nt) return;
+  const int a0 = 4 * (t / nt), c0 = 4 * (t - (t / nt) * nt);
+  double accR[4][4], accI[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      accR[i][j] = 0.0;
+      accI[i][j] = 0.0;
+    }
+  for (int k = 0; k < d; ++k) {
+    double dA[4], dB[4], xr[4], xi[4], yr[4], yi[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const bool ok = a0 + i < d;
+      dA[i] = ok ? sD[(a0 + i) * ld + k] : 0.0;                                // D[a][k]
+      yr[i] = ok ? static_cast<double>(sXr[(a0 + i) * ld + k]) : 0.0;          // X[a][k]
+      yi[i] = ok ? static_cast<double>(sXi[(a0 + i) * ld + k]) : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool ok = c0 + j < d;
+      dB[j] = ok ? sD[k * ld + c0 + j] : 0.0;                                  // D[k][c]
+      xr[j] = ok ? static_cast<double>(sXr[k * ld + c0 + j]) : 0.0;            // X[k][c]
+      xi[j] = ok ? static_cast<double>(sXi[k * ld + c0 + j]) : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        accR[i][j] += dA[i] * xr[j] - yr[i] * dB[j];
+        accI[i][j] += dA[i] * xi[j] - yi[i] * dB[j];
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (a0 + i < d && c0 + j < d) {
+        const int e = (a0 + i) * d + c0 + j;
+        dst[base + e] = static_cast<T>(accR[i][j]);
+        dst[base + dd + e] = static_cast<T>(accI[i][j]);
+      }
+}
+
 // ---------------------------------------------------------------------------
 // tr(A rho_0) per trajectory, FP64.
 // ---------------------------------------------------------------------------
@@ -432,8 +500,24 @@ template <typename T>
 void launch_commutator(const double* D, int transpose, const T* src, T* dst, int d, long long n_mats,
                        hipStream_t stream) {
   if (n_mats == 0) return;
-  hipLaunchKernelGGL((commutator_kernel<T>), dim3(static_cast<unsigned>(n_mats)), dim3(256), 0, stream,
-                     D, transpose, src, dst, d);
+  // LDS-staged kernel when D (double) and the matrix (T) fit in 160 KB;
+  // src and dst must not overlap (every caller writes another buffer)
+  const size_t lds = static_cast<size_t>(d) * (d + 1) * (sizeof(double) + 2 * sizeof(T));
+  const int nt = (d + 3) / 4;
+  const int threads = ((nt * nt + 63) / 64) * 64;
+  if (lds <= 160 * 1024 && threads <= 512) {
+    static bool configured = false;
+    if (!configured) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&commutator_tiled_kernel<T>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      configured = true;
+    }
+    hipLaunchKernelGGL((commutator_tiled_kernel<T>), dim3(static_cast<unsigned>(n_mats)), dim3(threads), lds,
+                       stream, D, transpose, src, dst, d);
+  } else {
+    hipLaunchKernelGGL((commutator_kernel<T>), dim3(static_cast<unsigned>(n_mats)), dim3(256), 0, stream,
+                       D, transpose, src, dst, d);
+  }
   check_launch("commutator kernel");
 }
 

@@ -169,9 +169,12 @@ def test_full_size_batched_step_sampled(full_size_refs, kernel):
     assert np.array_equal(got5, got0)
 
 
+@pytest.mark.parametrize("which,depth", [("cfg1", None), ("cfg2", 2), ("cfg3", 1), ("paper_scale", 1)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_dipole_and_trace_parity(prec):
-    params = _params("cfg2", 2)
+def test_dipole_and_trace_parity(which, depth, prec):
+    # d = 6, 25, 80, 64: the LDS-staged commutator kernel (d = 80 in FP64
+    # fills 155 KB of LDS); larger d use the plain kernel (edge-model tests)
+    params = _params(which, depth)
     o = om.build(params)
     m = P.heom_model_build(params)
     x = w.random_hierarchy(2, len(o.hier), o.d, seed=9)
