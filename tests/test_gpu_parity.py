@@ -577,3 +577,34 @@ def test_progress_reports_in_stationary_solve():
     assert done == sorted(done) and all(x % 200 == 0 for x in done)
     # one report per crossing of a multiple of 300 steps, at the next application boundary
     assert len(done) == len({x // 300 for x in done})
+
+
+def test_krylov_stationary_state_rate_filtered():
+    params = _params("cfg1", rate_cut=3.0)
+    params["dt"] = 0.05
+    params["decomp"] = "pade"
+    o = om.build(params)
+    assert len(o.hier) < len(om.build(dict(params, rate_cut=0.0)).hier)
+    ref = oh.stationary_state(o)
+    m = P.heom_model_build(params)
+    rho, applies, res = P.heom_equilibrate_krylov(m, tol=1e-11)
+    assert res <= 1e-11 and applies > 0
+    assert np.max(np.abs(rho.download()[0] - ref)) < 1e-8 * np.max(np.abs(ref))
+
+
+def test_batch_with_rate_filtered_instance():
+    insts = [_params("cfg2", 3, rate_cut=1.5), _params("cfg2", 3), _params("cfg1", 3, rate_cut=2.5)]
+    for p in insts:
+        p["dt"] = 0.05
+    models = [P.heom_model_build(p) for p in insts]
+    oracles = [om.build(p) for p in insts]
+    states, refs = [], []
+    for i, (m, o) in enumerate(zip(models, oracles)):
+        x = w.random_hierarchy(2, len(o.hier), o.d, seed=40 + i, hermitian=True, scale_by_depth=_depth_scale(o))
+        s = P.State(m, 2, "fp32")
+        s.upload(x)
+        states.append(s)
+        refs.append(oh.propagate(o, x, 4))
+    P.heom_batch_propagate(P.heom_batch_create(models), states, 4)
+    for s, ref in zip(states, refs):
+        assert _relerr(s.download(), ref) < 1e-5
