@@ -268,8 +268,6 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
         Rim[jj] = M::mma(aRe, hB, Rim[jj]);
       }
     }
-    // keep the scheduler from hoisting the LDS operands of many k-slices
-    __builtin_amdgcn_sched_barrier(0);
   }
   // damping -(g + i gi) rho; gi != 0 only for complex rates (Brownian baths)
   const T g = op.gamma[n];
@@ -289,6 +287,11 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
       }
     }
 
+  // The neighbour phase (global loads, LDS accumulation, v_s contractions)
+  // runs at raised wave priority so that it is issued ahead of the other
+  // workgroup's matrix-core phase on the same CU (measured: 1.5-4% per
+  // launch); the epilogue drops back to the default.
+  __builtin_amdgcn_s_setprio(1);
   // ---- couplings to the hierarchy neighbours ----------------------------
   // Each wave forms X_s (and Y_s) for its slab rows from 16-byte neighbour
   // loads: in registers, staged once per mode in the LDS planes, or
@@ -500,6 +503,7 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
     }
   }
 
+  __builtin_amdgcn_s_setprio(0);
   // ---- epilogue: out = y + coef * L ---------------------------------------
   // transpose the accumulators through LDS so that y and out move in
   // 16-byte vectors (slab rows).  Only the d x d block is written: the
