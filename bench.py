@@ -31,8 +31,8 @@ sys.path.insert(0, ROOT)
 # scaled by the counters' readings for kernels of known size.  Keyed by the
 # kernel source hash: a changed kernel reports traffic null until re-profiled.
 PROFILED_TRAFFIC = {  # source hash -> kernel choice -> bytes per launch
-    "b53a0fd195dabf58": {
-        "mfma": {"read_GB": 332.0, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
+    "e4550417f003fd40": {
+        "mfma": {"read_GB": 331.6, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
         "mfma_dyn": {"read_GB": 327.1, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
     },
 }
