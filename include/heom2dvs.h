@@ -368,7 +368,8 @@ int heom_batch_response_2d(heom_batch* batch, const heom_state* const* rho_eq, c
  *   HEOM_KERNEL_MFMA    : matrix-core kernel (v_mfma 16x16x4, persistent
  *                         workgroups of ceil(d/16) waves), d zero-padded to a
  *                         multiple of 16; compile-time mode shapes for
- *                         (4,4,5), (5,5) and (6) levels, runtime shape otherwise.
+ *                         (4,4,5) levels in FP64 and (6) levels, runtime shape
+ *                         otherwise.
  *   HEOM_KERNEL_MFMA_DYN: the matrix-core kernel with the runtime mode shape
  *                         even where a compile-time one exists.
  * Models start on HEOM_KERNEL_MFMA where it fits the LDS (FP32 d <= 112,

@@ -686,11 +686,13 @@ void launch_rhs_mfma(const DevOps<T>& op, const T* Hp, const T* in, const T* y, 
   if (wg < 1) wg = 1;
   if (wg > 8) wg = 8;
   const bool specialised = variant != 1;
-  // compile-time shapes of the common workloads
-  if (specialised && StaticShape<3, 4, 4, 5>::matches(op.n_modes, op.dims)) {
+  // compile-time shapes where they measured faster than the runtime shape
+  // (MI355X): (4,4,5) in FP64 and (6).  The runtime shape keeps fewer
+  // registers live and won for (4,4,5) in FP32 (101.0 vs 103.8 ms per launch
+  // at 128 trajectories) and for (5,5) in both precisions (FP32 15.0 vs
+  // 22.7 ms at 2048 trajectories, FP64 7.5 vs 12.6 ms at 512).
+  if (specialised && sizeof(T) == 8 && StaticShape<3, 4, 4, 5>::matches(op.n_modes, op.dims)) {
     launch_shape<T, 5, StaticShape<3, 4, 4, 5>>(op, Hp, in, y, out, c, n_items, wg, stream);
-  } else if (specialised && StaticShape<2, 5, 5>::matches(op.n_modes, op.dims)) {
-    launch_shape<T, 2, StaticShape<2, 5, 5>>(op, Hp, in, y, out, c, n_items, wg, stream);
   } else if (specialised && StaticShape<1, 6>::matches(op.n_modes, op.dims)) {
     launch_shape<T, 1, StaticShape<1, 6>>(op, Hp, in, y, out, c, n_items, wg, stream);
   } else {
