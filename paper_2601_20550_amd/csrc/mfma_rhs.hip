@@ -531,8 +531,11 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
       for (int k = 0; k < RV; ++k) {
         const int e = (lane + 64 * k) * VW;
         if (e < sb_elems) {
-          yr[k] = *reinterpret_cast<const vec_t*>(y + ob + e);
-          yi[k] = *reinterpret_cast<const vec_t*>(y + ob + dd + e);
+          // y and out are streamed (read and written once per launch, 33 GB at
+          // the benchmark size): non-temporal accesses leave the caches to the
+          // neighbour matrices, which are read up to 2M times
+          yr[k] = __builtin_nontemporal_load(reinterpret_cast<const vec_t*>(y + ob + e));
+          yi[k] = __builtin_nontemporal_load(reinterpret_cast<const vec_t*>(y + ob + dd + e));
         }
       }
     }
@@ -552,8 +555,8 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
           vset<T, VW>(orr, i, lre);
           vset<T, VW>(oi, i, lim);
         }
-        *reinterpret_cast<vec_t*>(out + ob + e) = orr;
-        *reinterpret_cast<vec_t*>(out + ob + dd + e) = oi;
+        __builtin_nontemporal_store(orr, reinterpret_cast<vec_t*>(out + ob + e));
+        __builtin_nontemporal_store(oi, reinterpret_cast<vec_t*>(out + ob + dd + e));
       }
     }
   }
