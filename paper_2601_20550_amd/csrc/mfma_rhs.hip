@@ -97,12 +97,13 @@ struct DynShape {
   __device__ int d() const { return d_; }
 };
 
-// Row padding of the LDS planes: DP + 1 spreads the column reads of the
-// matrix-core operands over the banks; for FP32 at NB = 5, DP + 4 keeps every
-// row 16-byte aligned so that the slab phases (staging, neighbour sums,
-// epilogue) use 16-byte LDS accesses, which measured 6% faster per launch
-// with a third of the bank-conflict cycles (two workgroups still fit).
-constexpr int lds_pad(size_t elem, int nb) { return (elem == 4 && nb == 5) ? 4 : 1; }
+// Row padding of the LDS planes: 16 bytes (4 FP32 or 2 FP64 elements) keep
+// every row 16-byte aligned, so that the slab phases (staging, neighbour sums,
+// the Y pass, epilogue) use 16-byte LDS accesses: FP32 at NB = 5 measured 6%
+// faster per launch with half the bank-conflict cycles (two workgroups still
+// fit), FP64 at NB = 5 2% faster; the largest layouts (FP32 NB = 7, FP64
+// NB = 5) still fit 160 KB.
+constexpr int lds_pad(size_t elem, int) { return elem == 4 ? 4 : 2; }
 
 // LDS layout (elements of T): rho planes Re, Im and H, each DP x LD with
 // LD = DP + lds_pad, then v_s (4 x 64 values).
@@ -404,10 +405,15 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
         const int e = (lane + 64 * k) * VW;
         if (e < sb_elems) {
           const int r = srow0 + e / d, c = e - (e / d) * d;
+          if constexpr (VL) {
+            *reinterpret_cast<vec_t*>(&sRe[r * LD + c]) = xr[k];
+            *reinterpret_cast<vec_t*>(&sIm[r * LD + c]) = xi[k];
+          } else {
 #pragma unroll
-          for (int i = 0; i < VW; ++i) {
-            sRe[r * LD + c + i] = vget<T, VW>(xr[k], i);
-            sIm[r * LD + c + i] = vget<T, VW>(xi[k], i);
+            for (int i = 0; i < VW; ++i) {
+              sRe[r * LD + c + i] = vget<T, VW>(xr[k], i);
+              sIm[r * LD + c + i] = vget<T, VW>(xi[k], i);
+            }
           }
         }
       }
@@ -443,10 +449,15 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
           const int e = (lane + 64 * k) * VW;
           if (e < sb_elems) {
             const int r = srow0 + e / d, c = e - (e / d) * d;
+            if constexpr (VL) {
+              *reinterpret_cast<vec_t*>(&sRe[r * LD + c]) = xr[k] + wr[k];
+              *reinterpret_cast<vec_t*>(&sIm[r * LD + c]) = xi[k] + wi[k];
+            } else {
 #pragma unroll
-            for (int i = 0; i < VW; ++i) {
-              sRe[r * LD + c + i] = vget<T, VW>(xr[k], i) + vget<T, VW>(wr[k], i);
-              sIm[r * LD + c + i] = vget<T, VW>(xi[k], i) + vget<T, VW>(wi[k], i);
+              for (int i = 0; i < VW; ++i) {
+                sRe[r * LD + c + i] = vget<T, VW>(xr[k], i) + vget<T, VW>(wr[k], i);
+                sIm[r * LD + c + i] = vget<T, VW>(xi[k], i) + vget<T, VW>(wi[k], i);
+              }
             }
           }
         }
