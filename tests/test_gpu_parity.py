@@ -608,3 +608,29 @@ def test_batch_with_rate_filtered_instance():
     P.heom_batch_propagate(P.heom_batch_create(models), states, 4)
     for s, ref in zip(states, refs):
         assert _relerr(s.download(), ref) < 1e-5
+
+
+@pytest.mark.parametrize("keep", [(4, 5), (6, 6), (4, 4, 3)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kernel", ["mfma", "mfma_dyn"])
+def test_rhs_parity_padded_multiple_of_four(keep, prec, kernel):
+    # d = 20, 36, 48: a multiple of four (16-byte rows in global memory and in
+    # the padded LDS planes) but, for 20 and 36, not of 16 (zero-padded tiles)
+    params = _params("cfg3" if len(keep) == 3 else "cfg2", 2)
+    for mode, k in zip(params["modes"], keep):
+        mode["n_keep"] = k
+    o = om.build(params)
+    m = P.heom_model_build(params)
+    P.heom_model_set_kernel(m, prec, kernel)
+    B = 600  # several matrices per persistent workgroup
+    x = w.random_hierarchy(2, len(o.hier), o.d, seed=31, scale_by_depth=_depth_scale(o))
+    xin = P.State(m, B, prec)
+    xout = P.State(m, B, prec)
+    xin.set_ground()
+    xin.upload_range(0, x[:1])
+    xin.upload_range(B - 1, x[1:])
+    P.heom_rhs(m, xin, xout)
+    ref = oh.rhs(o, x)
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    assert _relerr(xout.download_range(0, 1)[0], ref[0]) < tol
+    assert _relerr(xout.download_range(B - 1, 1)[0], ref[1]) < tol
