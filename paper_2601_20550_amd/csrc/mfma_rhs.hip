@@ -265,22 +265,58 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
     Rre[jj] = acc_t{0, 0, 0, 0};
     Rim[jj] = acc_t{0, 0, 0, 0};
   }
+  if constexpr (sizeof(T) == 4 && WPR == 2 && (LD % 4) == 0) {
+    // k = 16 blk + 4 lq + t: each lane's four k of a block are contiguous, so
+    // the A operands (rows of H, Re, Im) and H[k][col] = H[col][k] (H is
+    // symmetric) come from 16-byte LDS reads (FP32 with two waves per row
+    // block: d = 64 measured 140.0 -> 134.4 ms per launch; the one-wave
+    // shape of d = 80 gained nothing and keeps the loop below)
+    using v4 = typename Vec<T, 4>::type;
 #pragma unroll
-  for (int kk = 0; kk < 4 * NB; ++kk) {
-    const int k = 4 * kk + lq;
-    const T hA = sH[(rows0 + lr) * LD + k];
-    const T nhA = -hA;
-    const T aRe = sRe[(rows0 + lr) * LD + k];
-    const T naIm = -sIm[(rows0 + lr) * LD + k];
+    for (int blk = 0; blk < NB; ++blk) {
+      const int kb = 16 * blk + 4 * lq;
+      const v4 hA4 = *reinterpret_cast<const v4*>(&sH[(rows0 + lr) * LD + kb]);
+      const v4 aRe4 = *reinterpret_cast<const v4*>(&sRe[(rows0 + lr) * LD + kb]);
+      const v4 aIm4 = *reinterpret_cast<const v4*>(&sIm[(rows0 + lr) * LD + kb]);
+      v4 hB4[JT];
 #pragma unroll
-    for (int jj = 0; jj < JT; ++jj) {
-      if (j0 + jj < NB) {
-        const int j = j0 + jj;
-        const T hB = sH[k * LD + 16 * j + lr];
-        Rre[jj] = M::mma(hA, sIm[k * LD + 16 * j + lr], Rre[jj]);
-        Rre[jj] = M::mma(naIm, hB, Rre[jj]);
-        Rim[jj] = M::mma(nhA, sRe[k * LD + 16 * j + lr], Rim[jj]);
-        Rim[jj] = M::mma(aRe, hB, Rim[jj]);
+      for (int jj = 0; jj < JT; ++jj)
+        if (j0 + jj < NB) hB4[jj] = *reinterpret_cast<const v4*>(&sH[(16 * (j0 + jj) + lr) * LD + kb]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int k = kb + t;
+        const T hA = hA4[t], nhA = -hA4[t], aRe = aRe4[t], naIm = -aIm4[t];
+#pragma unroll
+        for (int jj = 0; jj < JT; ++jj) {
+          if (j0 + jj < NB) {
+            const int j = j0 + jj;
+            const T hB = hB4[jj][t];
+            Rre[jj] = M::mma(hA, sIm[k * LD + 16 * j + lr], Rre[jj]);
+            Rre[jj] = M::mma(naIm, hB, Rre[jj]);
+            Rim[jj] = M::mma(nhA, sRe[k * LD + 16 * j + lr], Rim[jj]);
+            Rim[jj] = M::mma(aRe, hB, Rim[jj]);
+          }
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < 4 * NB; ++kk) {
+      const int k = 4 * kk + lq;
+      const T hA = sH[(rows0 + lr) * LD + k];
+      const T nhA = -hA;
+      const T aRe = sRe[(rows0 + lr) * LD + k];
+      const T naIm = -sIm[(rows0 + lr) * LD + k];
+#pragma unroll
+      for (int jj = 0; jj < JT; ++jj) {
+        if (j0 + jj < NB) {
+          const int j = j0 + jj;
+          const T hB = sH[k * LD + 16 * j + lr];
+          Rre[jj] = M::mma(hA, sIm[k * LD + 16 * j + lr], Rre[jj]);
+          Rre[jj] = M::mma(naIm, hB, Rre[jj]);
+          Rim[jj] = M::mma(nhA, sRe[k * LD + 16 * j + lr], Rim[jj]);
+          Rim[jj] = M::mma(aRe, hB, Rim[jj]);
+        }
       }
     }
   }
