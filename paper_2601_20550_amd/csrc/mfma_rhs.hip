@@ -15,9 +15,8 @@
 // so only the entries with complex coefficients enter the second sum, and
 // gamma_n = sum_j n_j nu_j is complex only for complex rates (Brownian baths).
 //
-//   * H rho and rho H run on v_mfma 16x16x4 (FP32 or FP64): the fragment
-//     H[row block w][k-slice] stays in registers; rho (two real planes) and
-//     H (for the right product) are read from LDS.
+//   * H rho and rho H run on v_mfma 16x16x4 (FP32 or FP64) with H and rho
+//     (two real planes) staged in LDS, rows padded to 16-byte alignment.
 //   * The neighbour sums are formed from coalesced row-block loads (each
 //     neighbour matrix is read once per workgroup), staged in the rho planes
 //     of LDS, and contracted with v_s on the VALU.  The mode structure
