@@ -7,10 +7,13 @@ the batched t2/t3 propagation that dominates a 2D spectrum.  One "step" is one
 RK4 step of the whole batch (4 fused RHS launches).  value = ADO-updates/s =
 trajectories x ADOs x steps / wall time.
 
-Also reported: seconds per 2D spectrum (t2 = 0, full 128x128 grid, FP32
-propagation with FP64 pairing) measured end to end; the roofline of the
-dominant kernel from HIP-event timings of its launches inside the timed
-region; and the CPU oracle's rate on a bounded sample.
+Also reported: seconds per 2D spectrum (full 128x128 grid, FP32 propagation
+with FP64 pairing) measured end to end for t2 = 0 and for the t2 set {0, 50 fs}
+(the batched t2 propagation in the timed region), the FP32 error of the t2 = 0
+spectrum against the FP64 path, the equilibration with its convergence flag, a
+short FP64 propagation leg with its own roofline, the roofline of the dominant
+kernel from HIP-event timings of its launches inside the timed region, and the
+CPU oracle's rate on a bounded sample (all cores and one core).
 """
 
 from __future__ import annotations
@@ -71,29 +74,37 @@ def kernel_source_hash():
 
 
 def cpu_baseline(params, budget_s=30.0):
-    """Oracle rate on a bounded sample: RHS evaluations of one trajectory."""
+    """Oracle rate on a bounded sample: RHS evaluations of one trajectory, with
+    the BLAS thread pool at its default size (all host cores it uses) and
+    limited to one thread."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import heom as oh
     from oracle import model as om
     import workloads as w
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+    cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     o = om.build(params)
     x = w.random_hierarchy(1, len(o.hier), o.d, seed=1)[0]
-    t0 = time.perf_counter()
-    n_rhs = 0
-    while True:
-        oh.rhs(o, x)
-        n_rhs += 1
-        if time.perf_counter() - t0 > budget_s / 3 or n_rhs >= 4:
-            break
-    dt = (time.perf_counter() - t0) / n_rhs
-    rate = len(o.hier) / (4.0 * dt)  # one ADO-update = one RK4 step = 4 RHS
-    return {"value": rate, "unit": "ADO-updates/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{n_rhs} oracle RHS evaluation(s) of one trajectory of the "
-                      f"{len(o.hier)}-ADO model ({dt:.1f} s each); 4 RHS = 1 RK4 step"}
+
+    def rate(limit_s, max_rhs):
+        t0 = time.perf_counter()
+        n_rhs = 0
+        while True:
+            oh.rhs(o, x)
+            n_rhs += 1
+            if time.perf_counter() - t0 > limit_s or n_rhs >= max_rhs:
+                break
+        dt = (time.perf_counter() - t0) / n_rhs
+        return len(o.hier) / (4.0 * dt), n_rhs, dt  # one ADO-update = one RK4 step = 4 RHS
+
+    r_all, n_all, dt_all = rate(budget_s / 3, 3)
+    with threadpool_limits(1):
+        r_one, n_one, dt_one = rate(budget_s / 3, 1)
+    return {"value": r_all, "unit": "ADO-updates/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{n_all} oracle RHS evaluation(s) of one trajectory of the "
+                      f"{len(o.hier)}-ADO model ({dt_all:.1f} s each); 4 RHS = 1 RK4 step",
+            "single_core": {"value": r_one, "unit": "ADO-updates/s", "cores": 1,
+                            "sample": f"{n_one} RHS evaluation(s) with the BLAS pool limited to one "
+                                      f"thread ({dt_one:.1f} s each)"}}
 
 
 def multi_instance(P, torch, precision, stream, compare=False):
@@ -166,6 +177,116 @@ def gradient_timing(P, torch, stream):
             "finite": bool(np.isfinite(g["H"]).all() and np.isfinite(g["mu"]).all())}
 
 
+def fp64_leg(P, torch, m, steps, flops_per_traj):
+    """The plain FP64 propagation of the same model: 32 trajectories (the FP64
+    batch is chunked by memory in the response path), its own HIP-event roofline
+    against the FP64 peak."""
+    B = 32
+    prev = P.heom_model_get_kernel(m, "fp64")
+    s = P.State(m, B, "fp64")
+    s.set_ground()
+    P.heom_propagate(m, s, 1)
+    torch.cuda.synchronize()
+    P.heom_timing_enable(m, True)
+    t0 = time.perf_counter()
+    P.heom_propagate(m, s, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k_ms, n_launch, _ = P.heom_timing_read(m)
+    P.heom_timing_enable(m, False)
+    del s
+    avg = k_ms / 1e3 / max(n_launch, 1)
+    achieved = flops_per_traj * B / avg / 1e12
+    return {"value": B * m.n_ado * steps / wall, "unit": "ADO-updates/s", "trajectories": B, "steps": steps,
+            "ms_per_step": wall / steps * 1e3, "kernel_choice": prev,
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s",
+                         "frac": achieved / PEAKS["fp64_tflops"], "avg_launch_ms": avg * 1e3,
+                         "launches": n_launch}}
+
+
+def spectrum_legs(P, torch, w, m, params, grid, args):
+    """rho_eq by GMRES (FP64), then 2D spectra of the full 128 x 128 grid: the
+    t2 = 0 spectrum alone, the first --spectrum-t2 t2 values in one call (the
+    batched t2 propagation of 2 x 128 trajectories in the timed region), and
+    the FP32 error of the t2 = 0 spectrum against the FP64 path."""
+    out = {}
+    progress = lambda ph, done, tot: print(f"{ph}: {done}/{tot} RK4 steps", file=sys.stderr,  # noqa: E731
+                                           flush=True)
+    # rho_eq: 100 RK4 steps from |0><0|, then GMRES corrections, each call one
+    # restart cycle of --eq-chunk applications of 500 steps, until the residual
+    # reaches --eq-tol or --eq-seconds have passed (progress on stderr)
+    torch.cuda.synchronize()
+    t_eq = time.perf_counter()
+    rho = P.State(m, 1, "fp64")
+    rho.set_ground()
+    P.heom_propagate(m, rho, 100)
+    eq_applies, eq_res = 0, float("inf")
+    P.heom_model_set_progress(m, progress, 5000)
+    while True:
+        a, eq_res = P.heom_stationary_refine(m, rho, tol=args.eq_tol, max_applies=args.eq_chunk,
+                                             restart=args.eq_chunk)
+        eq_applies += a
+        print(f"equilibration: {eq_applies} applications, residual {eq_res:.3e}", file=sys.stderr, flush=True)
+        if eq_res <= args.eq_tol or time.perf_counter() - t_eq > args.eq_seconds or a == 0:
+            break
+    P.heom_model_set_progress(m, None)
+    torch.cuda.synchronize()
+    t_eq = time.perf_counter() - t_eq
+    converged = bool(eq_res <= args.eq_tol)
+    out["equilibration"] = {"method": "GMRES on I - Phi^500 (FP64)", "s": t_eq,
+                            "rk4_steps": 100 + 500 * eq_applies, "residual": eq_res, "tol": args.eq_tol,
+                            "converged": converged}
+    dt_s = grid["steps_per_sample"] * params["dt"]
+    g1 = dict(grid)
+    g1["t2_steps"] = [0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    R = P.heom_response_2d(m, rho, g1, args.precision, "adjoint")
+    S = P.heom_spectrum_2d(R[0, 0], R[0, 1], dt_s)
+    torch.cuda.synchronize()
+    out["s_2d_spectrum_t2_0"] = time.perf_counter() - t0
+    out["spectrum_config"] = {"grid": [g1["n1"], g1["n3"]], "method": "adjoint (t3 by the transposed "
+                              "propagation of the detection functional)", "precision": args.precision,
+                              "rho_eq_converged": converged, "finite": bool(np.isfinite(S).all())}
+    if args.eps_spec and args.precision == "fp32":
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        R64 = P.heom_response_2d(m, rho, g1, "fp64", "adjoint")
+        S64 = P.heom_spectrum_2d(R64[0, 0], R64[0, 1], dt_s)
+        torch.cuda.synchronize()
+        out["eps_spec"] = {"t2": 0, "grid": [g1["n1"], g1["n3"]],
+                           "value": float(np.max(np.abs(S - S64)) / np.max(np.abs(S64))),
+                           "R_rel": float(np.max(np.abs(R - R64)) / np.max(np.abs(R64))),
+                           "reference": "FP64 GPU path", "target": 1e-4, "s_fp64": time.perf_counter() - t0}
+    if args.spectrum_t2 > 1:
+        # several t2 values in one call: the t1 snapshots of both pathways are
+        # propagated through t2 as one 128-trajectory batch per pathway
+        g2 = dict(grid)
+        g2["t2_steps"] = list(grid["t2_steps"][:args.spectrum_t2])
+        P.heom_model_set_progress(m, progress, 100)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        R = P.heom_response_2d(m, rho, g2, args.precision, "adjoint")
+        S = [P.heom_spectrum_2d(R[q, 0], R[q, 1], dt_s) for q in range(R.shape[0])]
+        torch.cuda.synchronize()
+        t_set = time.perf_counter() - t0
+        P.heom_model_set_progress(m, None)
+        dt_fs = params["dt"] * w.FS_PER_TIME_UNIT
+        all_t2 = list(grid["t2_steps"])
+        # the t2 propagation is incremental: t2 up to max(t2) costs max(t2) batched steps
+        per_step = (t_set - out["s_2d_spectrum_t2_0"]) / max(1, g2["t2_steps"][-1])
+        out["s_2d_spectra_t2_set"] = {
+            "t2_fs": [round(x * dt_fs, 1) for x in g2["t2_steps"]], "s": t_set,
+            "s_per_2d_spectrum": t_set / len(g2["t2_steps"]),
+            "extrapolated_all_t2_s": out["s_2d_spectrum_t2_0"] + per_step * all_t2[-1],
+            "all_t2_fs": [round(x * dt_fs, 1) for x in all_t2],
+            "rho_eq_converged": converged, "finite": bool(all(np.isfinite(x).all() for x in S))}
+        out["s_per_2d_spectrum"] = t_set / len(g2["t2_steps"])
+    else:
+        out["s_per_2d_spectrum"] = out["s_2d_spectrum_t2_0"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,13 +296,18 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--depth", type=int, default=6)
     ap.add_argument("--spectrum", type=int, default=1, help="also time one full 2D spectrum")
-    ap.add_argument("--spectrum-t2", type=int, default=1,
+    ap.add_argument("--spectrum-t2", type=int, default=2,
                     help="number of the workload's t2 values in the timed response call "
                          "(1: t2 = 0 only; cfg3 has 0, 50, 100, 200 fs)")
     ap.add_argument("--eq-tol", type=float, default=1e-8)
-    ap.add_argument("--eq-seconds", type=float, default=60.0)
-    ap.add_argument("--eq-chunk", type=int, default=10,
-                    help="GMRES applications per refinement call (100 = one full restart cycle)")
+    ap.add_argument("--eq-seconds", type=float, default=300.0)
+    ap.add_argument("--eq-chunk", type=int, default=100,
+                    help="GMRES applications per refinement call; each call is one restart cycle "
+                         "(restarts every 10 applications stagnate on the slow population modes)")
+    ap.add_argument("--fp64-steps", type=int, default=3,
+                    help="RK4 steps of a 32-trajectory FP64 leg with its own roofline (0: skip)")
+    ap.add_argument("--eps-spec", type=int, default=1,
+                    help="also compute the t2 = 0 spectrum in FP64 and report the FP32 error")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--multi", type=int, default=1,
                     help="1: also time the 64-instance uneven batch; 2: and one instance at a time")
@@ -214,7 +340,7 @@ def main():
     B = args.batch
     tune = None
     if args.kernel == "auto":
-        best, ms = P.heom_autotune(m, min(B, 8), args.precision, reps=1)
+        best, ms = P.heom_autotune(m, min(B, 8), args.precision, reps=3)
         tune = {"chosen": best, "ms_per_step_8traj": ms}
     else:
         P.heom_model_set_kernel(m, args.precision, args.kernel)
@@ -277,63 +403,10 @@ def main():
         line["roofline"]["traffic_unit"] = "bytes per launch (HBM, calibrated rocprofv3 counters)"
         line["roofline"]["hbm_GBs_at_traffic"] = line["roofline"]["traffic"] / avg_launch_s / 1e9
 
+    if args.fp64_steps > 0 and args.precision == "fp32":
+        line["fp64"] = fp64_leg(P, torch, m, args.fp64_steps, algorithmic_flops_per_rhs(m))
     if args.spectrum:
-        # rho_eq: 100 RK4 steps from |0><0|, then GMRES corrections in chunks of
-        # --eq-chunk applications of 500 steps until the residual reaches
-        # --eq-tol or --eq-seconds have passed (progress on stderr)
-        torch.cuda.synchronize()
-        t_eq = time.perf_counter()
-        rho = P.State(m, 1, "fp64")
-        rho.set_ground()
-        P.heom_propagate(m, rho, 100)
-        eq_applies, eq_res = 0, float("inf")
-        if args.eq_chunk > 10:
-            P.heom_model_set_progress(
-                m, lambda ph, done, tot: print(f"{ph}: {done}/{tot} RK4 steps", file=sys.stderr, flush=True),
-                5000)
-        while True:
-            a, eq_res = P.heom_stationary_refine(m, rho, tol=args.eq_tol, max_applies=args.eq_chunk,
-                                                 restart=max(10, args.eq_chunk))
-            eq_applies += a
-            print(f"equilibration: {eq_applies} applications, residual {eq_res:.3e}", file=sys.stderr,
-                  flush=True)
-            if eq_res <= args.eq_tol or time.perf_counter() - t_eq > args.eq_seconds or a == 0:
-                break
-        P.heom_model_set_progress(m, None)
-        torch.cuda.synchronize()
-        t_eq = time.perf_counter() - t_eq
-        g1 = dict(grid)
-        g1["t2_steps"] = [0]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        R = P.heom_response_2d(m, rho, g1, args.precision, "adjoint")
-        S = P.heom_spectrum_2d(R[0, 0], R[0, 1], grid["steps_per_sample"] * params["dt"])
-        torch.cuda.synchronize()
-        line["s_per_2d_spectrum"] = time.perf_counter() - t0
-        line["spectrum_config"] = {"t2": 0, "grid": [g1["n1"], g1["n3"]], "method": "adjoint",
-                                   "finite": bool(np.isfinite(S).all())}
-        if args.spectrum_t2 > 1:
-            # several t2 values in one call: the t2 branches are propagated
-            # incrementally (progress on stderr)
-            g2 = dict(grid)
-            g2["t2_steps"] = list(grid["t2_steps"][:args.spectrum_t2])
-            P.heom_model_set_progress(
-                m, lambda ph, done, tot: print(f"{ph}: {done}/{tot} RK4 steps", file=sys.stderr, flush=True),
-                50)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            R = P.heom_response_2d(m, rho, g2, args.precision, "adjoint")
-            S = [P.heom_spectrum_2d(R[q, 0], R[q, 1], grid["steps_per_sample"] * params["dt"])
-                 for q in range(R.shape[0])]
-            torch.cuda.synchronize()
-            P.heom_model_set_progress(m, None)
-            dt_fs = params["dt"] * w.FS_PER_TIME_UNIT
-            line["s_2d_spectra_t2_set"] = {
-                "t2_fs": [round(x * dt_fs, 1) for x in g2["t2_steps"]], "s": time.perf_counter() - t0,
-                "finite": bool(all(np.isfinite(x).all() for x in S))}
-        line["equilibration"] = {"method": "GMRES on I - Phi^500 (FP64)", "s": t_eq,
-                                 "rk4_steps": 100 + 500 * eq_applies, "residual": eq_res,
-                                 "tol": args.eq_tol}
+        line.update(spectrum_legs(P, torch, w, m, params, grid, args))
     del s
     if args.multi:
         line["multi_instance"] = multi_instance(P, torch, args.precision, stream.cuda_stream,

@@ -195,11 +195,21 @@ int heom_state_copy(heom_state* dst, const heom_state* src);
  * bilinear pairing <A, X> = sum_n sum_ab A_n[a,b] X_n[a,b]. */
 int heom_rhs(heom_model* model, const heom_state* in, heom_state* out, int adjoint);
 /* n_steps fixed-step fourth-order Runge-Kutta steps of d rho/dt = L rho (or
- * L^T rho) in place.  The step is evaluated as y + h L(y + h/2 L(y + h/3 L(y
- * + h/4 L y))), which equals the classic four-stage scheme for this linear,
- * time-independent generator.  HEOM_ERR_UNSTABLE if the state becomes
+ * L^T rho) in place (Sec. III: fixed-step Runge-Kutta integration of Eq.
+ * HEOM_DB).  The step is evaluated as y + h L(y + h/2 L(y + h/3 L(y + h/4 L
+ * y))), which equals the classic four-stage scheme for this linear,
+ * time-independent generator.  The arithmetic is the state's precision (the
+ * state carries it, so there is no separate precision argument).
+ * sample_every > 0 with trace_out != NULL records the detection trace
+ * tr(mu rho_{b, n=0}) (FP64 accumulation, Eq. R1's trace) of every trajectory
+ * b at steps 0, sample_every, 2 sample_every, ... <= n_steps:
+ * trace_out is caller-owned host memory of
+ * (n_steps / sample_every + 1) x n_traj complex values (interleaved re, im),
+ * sample-major.  sample_every <= 0 or trace_out == NULL records nothing.
+ * HEOM_ERR_PARAM for n_steps < 0; HEOM_ERR_UNSTABLE if the state becomes
  * non-finite (checked at the end). */
-int heom_propagate(heom_model* model, heom_state* state, int n_steps, int adjoint);
+int heom_propagate(heom_model* model, heom_state* state, int n_steps, int adjoint, int sample_every,
+                   double* trace_out);
 /* X <- D^x X = D X - X D on every ADO (transpose = 0), or
  * X <- (D^T)^x X (transpose = 1), D chosen by `op` (heom_operator). FP64
  * arithmetic on either precision. */
@@ -215,7 +225,10 @@ int heom_residual(heom_model* model, const heom_state* state, double* out);
  * min_steps are done) evaluate the residual max|L rho|; stop at the first
  * check <= tol or at max_steps.  Returns a new FP64 state with one
  * trajectory.  HEOM_ERR_NOCONV is returned (with the state still written)
- * when max_steps is reached above tol and require_convergence != 0. */
+ * when max_steps is reached above tol and require_convergence != 0.
+ * Times are counted in RK4 steps of the model's fixed dt: the time limit is
+ * t_max = max_steps dt and the equilibration time t_eq = (*steps_out) dt (a
+ * step count is exact, a time would have to be rounded to the step grid). */
 int heom_equilibrate(heom_model* model, double tol, int check_every, int min_steps,
                      int max_steps, int require_convergence, heom_state** rho_eq_out,
                      int* steps_out, double* residual_out);
@@ -326,6 +339,23 @@ typedef struct {
 int heom_response_2d_vjp(heom_model* model, const heom_state* rho_eq, const heom_grid* grid, const double* W,
                          int rho_is_stationary, double tol, int max_steps, heom_op_grad* out);
 
+/* Backward pass of heom_response_2d (the gradient of a loss L(R) of the
+ * responses with respect to model parameters; Sec. II.B: the generator of Eq.
+ * HEOM_DB is linear in H_S', V_s, c_j and nu_j, so every derivative is a
+ * pairing of forward and adjoint hierarchies): heom_response_2d_vjp with the
+ * weights W = conj(dL_dR), then heom_params_vjp along the directions dirs.
+ * params: the parameters `model` was built from; dL_dR: host
+ * [n_t2][2][n1][n3] complex, dL/dRe R + i dL/dIm R; dirs: n_theta parameter
+ * directions (d params / d theta_i, layout of params); step: central-
+ * difference step of the host build derivative; rho_is_stationary, tol and
+ * max_steps as in heom_response_2d_vjp.  dL_dtheta: caller-owned host
+ * [n_theta].  Errors and limits as heom_response_2d_vjp and
+ * heom_params_vjp. */
+int heom_response_2d_backward(const heom_params* params, heom_model* model, const heom_state* rho_eq,
+                              const heom_grid* grid, const double* dL_dR, int rho_is_stationary, double tol,
+                              int max_steps, const heom_params* dirs, int n_theta, double step,
+                              double* dL_dtheta);
+
 /* Adjoint of heom_spectrum_2d: weights W[P][j][k] (P = I, II; host,
  * [2][n1][n3] complex) with sum G . S_C(R_I, R_II) = Re sum W[P] R_P for the
  * real cotangent G ([2 n3][2 n1], e.g. dJ/dS_C).  Host computation, FP64. */
@@ -373,8 +403,11 @@ int heom_batch_response_2d(heom_batch* batch, const heom_state* const* rho_eq, c
  *   HEOM_KERNEL_MFMA_DYN: the matrix-core kernel with the runtime mode shape
  *                         even where a compile-time one exists.
  * Models start on HEOM_KERNEL_MFMA where it fits the LDS (FP32 d <= 112,
- * FP64 d <= 80) and on HEOM_KERNEL_GENERIC otherwise; heom_autotune measures
- * the candidates. */
+ * FP64 d <= 80) and every mode keeps at most 8 levels (the single-mode
+ * operators are staged in 8 x 8 LDS slots), and on HEOM_KERNEL_GENERIC
+ * otherwise; heom_model_set_kernel refuses a matrix-core kernel for a model
+ * outside these limits (HEOM_ERR_PARAM), and so does heom_batch_create.
+ * heom_autotune measures the candidates. */
 typedef enum {
   HEOM_KERNEL_AUTO = 0,
   HEOM_KERNEL_GENERIC = 1,

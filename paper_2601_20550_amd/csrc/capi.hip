@@ -277,8 +277,8 @@ void upload_model(heom_model* m) {
       for (int c = 0; c < d; ++c) hp[static_cast<size_t>(a) * DP + c] = hm.H[static_cast<size_t>(a) * d + c];
     m->Hp64 = upload_vec(hp, st);
     m->Hp32 = f32(hp);
-    if (!heom::mfma_supported<double>(d)) m->kernel[HEOM_FP64] = HEOM_KERNEL_GENERIC;
-    if (!heom::mfma_supported<float>(d)) m->kernel[HEOM_FP32] = HEOM_KERNEL_GENERIC;
+    if (!heom::mfma_supported<double>(d, hm.n_modes, hm.dims)) m->kernel[HEOM_FP64] = HEOM_KERNEL_GENERIC;
+    if (!heom::mfma_supported<float>(d, hm.n_modes, hm.dims)) m->kernel[HEOM_FP32] = HEOM_KERNEL_GENERIC;
   }
   {
     m->nb_tj = upload_vec(hm.fwd.tj, st);
@@ -512,6 +512,28 @@ void check_finite(heom_model* m, const T* x, int n_traj, const char* where) {
   if (!std::isfinite(r))
     throw HeomError(HEOM_ERR_UNSTABLE, std::string("non-finite hierarchy after ") + where +
                                            " (time step beyond the RK4 stability region?)");
+}
+
+template <typename T>
+void propagate_sampled(heom_model* m, heom_state* s, int n_steps, bool adjoint, int sample_every, double* trace_out) {
+  T* y = s->buf.as<T>();
+  if (sample_every <= 0 || !trace_out) {
+    rk4_steps_scratch<T>(m, y, s->n_traj, n_steps, adjoint);
+  } else {
+    // tr(mu rho_0) of every trajectory at steps 0, sample_every, ... <= n_steps
+    const int n_samples = n_steps / sample_every + 1;
+    DevBuf tr(static_cast<size_t>(n_samples) * s->n_traj * 2 * sizeof(double));
+    for (int k = 0; k < n_samples; ++k) {
+      if (k > 0) rk4_steps_scratch<T>(m, y, s->n_traj, sample_every, adjoint);
+      heom::launch_trace<T>(m->mu64[HEOM_OP_MU].as<double>(), y, m->hm.d, m->traj_elems(), s->n_traj,
+                            tr.as<double>() + static_cast<size_t>(k) * s->n_traj * 2, 1, m->stream);
+    }
+    const int rest = n_steps - (n_samples - 1) * sample_every;
+    if (rest > 0) rk4_steps_scratch<T>(m, y, s->n_traj, rest, adjoint);
+    hip_check(hipMemcpyAsync(trace_out, tr.p, tr.bytes, hipMemcpyDeviceToHost, m->stream), "copy");
+    hip_check(hipStreamSynchronize(m->stream), "sync");
+  }
+  check_finite<T>(m, y, s->n_traj, "propagation");
 }
 
 std::unique_ptr<heom_state> new_state(heom_model* m, int n_traj, int prec) {
@@ -1697,18 +1719,15 @@ int heom_rhs(heom_model* m, const heom_state* in, heom_state* out, int adjoint) 
   });
 }
 
-int heom_propagate(heom_model* m, heom_state* s, int n_steps, int adjoint) {
+int heom_propagate(heom_model* m, heom_state* s, int n_steps, int adjoint, int sample_every, double* trace_out) {
   return guarded([&] {
     require_device(m);
     require_state(m, s);
     if (n_steps < 0) throw HeomError(HEOM_ERR_PARAM, "n_steps must be >= 0");
-    if (s->precision == HEOM_FP64) {
-      rk4_steps_scratch<double>(m, s->buf.as<double>(), s->n_traj, n_steps, adjoint != 0);
-      check_finite<double>(m, s->buf.as<double>(), s->n_traj, "propagation");
-    } else {
-      rk4_steps_scratch<float>(m, s->buf.as<float>(), s->n_traj, n_steps, adjoint != 0);
-      check_finite<float>(m, s->buf.as<float>(), s->n_traj, "propagation");
-    }
+    if (s->precision == HEOM_FP64)
+      propagate_sampled<double>(m, s, n_steps, adjoint != 0, sample_every, trace_out);
+    else
+      propagate_sampled<float>(m, s, n_steps, adjoint != 0, sample_every, trace_out);
   });
 }
 
@@ -2068,6 +2087,36 @@ int heom_params_vjp(const heom_params* params, const heom_params* dirs, int n_di
   });
 }
 
+int heom_response_2d_backward(const heom_params* params, heom_model* m, const heom_state* rho_eq,
+                              const heom_grid* grid, const double* dL_dR, int rho_is_stationary, double tol,
+                              int max_steps, const heom_params* dirs, int n_theta, double step,
+                              double* dL_dtheta) {
+  return guarded([&] {
+    require_device(m);
+    if (!params || !grid || !dL_dR || !dirs || !dL_dtheta || n_theta < 1)
+      throw HeomError(HEOM_ERR_PARAM, "null argument or n_theta < 1");
+    if (grid->n_t2 < 1 || grid->n1 < 1 || grid->n3 < 1) throw HeomError(HEOM_ERR_PARAM, "bad grid");
+    // dL = sum (dL/dRe R dRe R + dL/dIm R dIm R) = Re sum conj(G) dR with
+    // G = dL/dRe R + i dL/dIm R, so the response weights are W = conj(G)
+    const size_t nr = static_cast<size_t>(grid->n_t2) * 2 * grid->n1 * grid->n3;
+    std::vector<double> W(2 * nr);
+    for (size_t k = 0; k < nr; ++k) {
+      W[2 * k] = dL_dR[2 * k];
+      W[2 * k + 1] = -dL_dR[2 * k + 1];
+    }
+    const int d = m->hm.d;
+    size_t nv = 0;
+    for (int s = 0; s < m->hm.n_modes; ++s) nv += static_cast<size_t>(m->hm.dims[s]) * m->hm.dims[s];
+    std::vector<double> dH(static_cast<size_t>(d) * d), dv(nv), dmu(static_cast<size_t>(d) * d),
+        dc(2 * static_cast<size_t>(m->hm.n_terms)), dnu(m->hm.n_terms);
+    heom_op_grad g{dH.data(), dv.data(), dmu.data(), dc.data(), dnu.data(), 0, 0.0};
+    int rc = heom_response_2d_vjp(m, rho_eq, grid, W.data(), rho_is_stationary, tol, max_steps, &g);
+    if (rc != HEOM_OK) throw HeomError(rc, g_last_error);
+    rc = heom_params_vjp(params, dirs, n_theta, step, &g, dL_dtheta);
+    if (rc != HEOM_OK) throw HeomError(rc, g_last_error);
+  });
+}
+
 int heom_batch_create(heom_model* const* models, int n_models, heom_batch** out) {
   return guarded([&] {
     if (!out || !models || n_models < 1) throw HeomError(HEOM_ERR_PARAM, "bad batch arguments");
@@ -2084,7 +2133,7 @@ int heom_batch_create(heom_model* const* models, int n_models, heom_batch** out)
         if (m->hm.dt != b->dt) throw HeomError(HEOM_ERR_PARAM, "batch models must share the time step");
         if (m->device != models[0]->device) throw HeomError(HEOM_ERR_PARAM, "batch models must share the device");
       }
-      if (!heom::mfma_supported<float>(m->hm.d) || (m->hm.d + 15) / 16 > 7)
+      if (!heom::mfma_supported<float>(m->hm.d, m->hm.n_modes, m->hm.dims) || (m->hm.d + 15) / 16 > 7)
         throw HeomError(HEOM_ERR_PARAM, "batch model dimension too large for the matrix-core kernel");
       b->models.push_back(m);
     }
@@ -2111,7 +2160,7 @@ int heom_batch_propagate(heom_batch* b, heom_state* const* states, int n_steps, 
     }
     if (prec == HEOM_FP64) {
       for (auto* m : b->models)
-        if (!heom::mfma_supported<double>(m->hm.d)) throw HeomError(HEOM_ERR_PARAM, "FP64 batch needs d <= 80");
+        if (!heom::mfma_supported<double>(m->hm.d, m->hm.n_modes, m->hm.dims)) throw HeomError(HEOM_ERR_PARAM, "FP64 batch needs d <= 80");
       BatchProp<double> bp;
       std::vector<double*> ys(n);
       for (int i = 0; i < n; ++i) ys[i] = states[i]->buf.as<double>();
@@ -2148,7 +2197,7 @@ int heom_batch_response_2d(heom_batch* b, const heom_state* const* rho_eq, const
     if (precision != HEOM_FP64 && precision != HEOM_FP32) throw HeomError(HEOM_ERR_PARAM, "bad precision");
     if (precision == HEOM_FP64)
       for (auto* m : b->models)
-        if (!heom::mfma_supported<double>(m->hm.d)) throw HeomError(HEOM_ERR_PARAM, "FP64 batch needs d <= 80");
+        if (!heom::mfma_supported<double>(m->hm.d, m->hm.n_modes, m->hm.dims)) throw HeomError(HEOM_ERR_PARAM, "FP64 batch needs d <= 80");
     // Instances go in groups whose buffers (Psi: n3, snapshots: n1, their two
     // RK4 scratch copies when t2 > 0, a few single states) fit in free memory.
     const size_t elem = precision == HEOM_FP64 ? sizeof(double) : sizeof(float);
@@ -2186,7 +2235,7 @@ int heom_model_set_kernel(heom_model* m, int precision, int kernel) {
     require_device(m);
     if (precision != HEOM_FP64 && precision != HEOM_FP32) throw HeomError(HEOM_ERR_PARAM, "bad precision");
     if (kernel < HEOM_KERNEL_AUTO || kernel > HEOM_KERNEL_MFMA_DYN) throw HeomError(HEOM_ERR_PARAM, "bad kernel");
-    const bool ok = precision == HEOM_FP64 ? heom::mfma_supported<double>(m->hm.d) : heom::mfma_supported<float>(m->hm.d);
+    const bool ok = precision == HEOM_FP64 ? heom::mfma_supported<double>(m->hm.d, m->hm.n_modes, m->hm.dims) : heom::mfma_supported<float>(m->hm.d, m->hm.n_modes, m->hm.dims);
     if (kernel == HEOM_KERNEL_AUTO) kernel = ok ? HEOM_KERNEL_MFMA : HEOM_KERNEL_GENERIC;
     if (kernel != HEOM_KERNEL_GENERIC && !ok) throw HeomError(HEOM_ERR_PARAM, "matrix-core kernel unsupported for this d");
     m->kernel[precision] = kernel;
@@ -2235,7 +2284,7 @@ int heom_autotune(heom_model* m, int n_traj, int precision, int reps, int* kerne
     m->timing = false;
     int best = saved;
     double best_ms = 1e300;
-    const bool ok = precision == HEOM_FP64 ? heom::mfma_supported<double>(m->hm.d) : heom::mfma_supported<float>(m->hm.d);
+    const bool ok = precision == HEOM_FP64 ? heom::mfma_supported<double>(m->hm.d, m->hm.n_modes, m->hm.dims) : heom::mfma_supported<float>(m->hm.d, m->hm.n_modes, m->hm.dims);
     for (int k = HEOM_KERNEL_GENERIC; k <= HEOM_KERNEL_MFMA_DYN; ++k) {
       if (k != HEOM_KERNEL_GENERIC && !ok) continue;
       m->kernel[precision] = k;

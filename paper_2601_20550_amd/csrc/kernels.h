@@ -32,12 +32,16 @@ template <typename T>
 void launch_rhs(const DevOps<T>& op, const T* in, const T* y, T* out, double coef, int n_traj,
                 hipStream_t stream);
 
+// True when the matrix-core kernel can run a model of product dimension d and
+// n_modes modes of dims[s] kept levels: the LDS planes fit 160 KB and every
+// single-mode operator fits its 8 x 8 LDS slot.
+template <typename T>
+bool mfma_supported(int d, int n_modes, const int* dims);
+
 // Same operation on the matrix cores: persistent workgroups of ceil(d/16)
 // waves, one matrix at a time.  Hp: H zero-padded to DP x DP, DP =
 // 16 ceil(d/16).  variant 1 forces the runtime mode-shape kernel; otherwise a
 // compile-time shape is used when one matches the model.
-template <typename T>
-bool mfma_supported(int d);
 template <typename T>
 void launch_rhs_mfma(const DevOps<T>& op, const T* Hp, const T* in, const T* y, T* out, double coef,
                      int n_traj, int variant, hipStream_t stream);

@@ -756,8 +756,13 @@ void launch_dyn(const DevOps<T>& op, const T* Hp, const T* in, const T* y, T* ou
 }  // namespace
 
 template <typename T>
-bool mfma_supported(int d) {
+bool mfma_supported(int d, int n_modes, const int* dims) {
   if (d < 1 || d > 128) return false;
+  // v_s is staged in a fixed slot of 64 values per mode (Lds::VOFF): at most
+  // four modes of at most 8 kept levels each
+  if (n_modes < 1 || n_modes > 4) return false;
+  for (int s = 0; s < n_modes; ++s)
+    if (dims[s] < 1 || dims[s] > 8) return false;
   const int NB = (d + 15) / 16;
   const size_t DP = 16 * NB;
   const size_t lds = (3 * DP * (DP + lds_pad(sizeof(T), NB)) + 4 * 64) * sizeof(T);
@@ -863,8 +868,8 @@ void launch_rhs_mfma_multi(const InstDesc<T>* desc, int n_inst, int nb, int vw, 
 template void launch_rhs_mfma_multi<float>(const InstDesc<float>*, int, int, int, double, long long, hipStream_t);
 template void launch_rhs_mfma_multi<double>(const InstDesc<double>*, int, int, int, double, long long, hipStream_t);
 
-template bool mfma_supported<float>(int);
-template bool mfma_supported<double>(int);
+template bool mfma_supported<float>(int, int, const int*);
+template bool mfma_supported<double>(int, int, const int*);
 template void launch_rhs_mfma<float>(const DevOps<float>&, const float*, const float*, const float*, float*,
                                      double, int, int, hipStream_t);
 template void launch_rhs_mfma<double>(const DevOps<double>&, const double*, const double*, const double*,

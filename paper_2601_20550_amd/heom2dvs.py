@@ -106,7 +106,7 @@ _SIGS = {
     "heom_state_set_ground": (C.c_int, [C.c_void_p]),
     "heom_state_copy": (C.c_int, [C.c_void_p, C.c_void_p]),
     "heom_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
-    "heom_propagate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int]),
+    "heom_propagate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p]),
     "heom_apply_dipole": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int]),
     "heom_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "heom_residual": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
@@ -132,6 +132,9 @@ _SIGS = {
     "heom_spectrum_2d_vjp": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_void_p]),
     "heom_params_vjp": (C.c_int, [C.POINTER(heom_params), C.c_void_p, C.c_int, C.c_double,
                                   C.POINTER(heom_op_grad), C.c_void_p]),
+    "heom_response_2d_backward": (C.c_int, [C.POINTER(heom_params), C.c_void_p, C.c_void_p,
+                                            C.POINTER(heom_grid), C.c_void_p, C.c_int, C.c_double,
+                                            C.c_int, C.c_void_p, C.c_int, C.c_double, C.c_void_p]),
     "heom_batch_create": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]),
     "heom_batch_free": (None, [C.c_void_p]),
     "heom_batch_propagate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int]),
@@ -369,8 +372,17 @@ def heom_rhs(model, x_in: State, x_out: State, adjoint=False):
     _check(_lib.heom_rhs(model.handle, x_in.handle, x_out.handle, int(bool(adjoint))))
 
 
-def heom_propagate(model, state: State, n_steps: int, adjoint=False):
-    _check(_lib.heom_propagate(model.handle, state.handle, int(n_steps), int(bool(adjoint))))
+def heom_propagate(model, state: State, n_steps: int, adjoint=False, sample_every=0):
+    """n_steps RK4 steps in place; with sample_every > 0 returns the detection
+    traces tr(mu rho_0) as a complex array [n_steps // sample_every + 1][n_traj]."""
+    if sample_every and sample_every > 0:
+        n_traj = state.shape()[0]
+        out = np.zeros((int(n_steps) // int(sample_every) + 1) * n_traj * 2)
+        _check(_lib.heom_propagate(model.handle, state.handle, int(n_steps), int(bool(adjoint)),
+                                   int(sample_every), _ptr(out)))
+        return (out[0::2] + 1j * out[1::2]).reshape(-1, n_traj)
+    _check(_lib.heom_propagate(model.handle, state.handle, int(n_steps), int(bool(adjoint)), 0, None))
+    return None
 
 
 def heom_apply_dipole(model, state: State, op="mu", transpose=False):
@@ -556,6 +568,26 @@ def heom_params_vjp(params, dirs, grad, step=1e-6):
     return out
 
 
+def heom_response_2d_backward(params, model, rho_eq, grid, dL_dR, dirs, stationary=True, tol=1e-11,
+                              max_steps=1000000, step=1e-6):
+    """dL/dtheta_i for a loss L(R) of heom_response_2d's output: dL_dR is the
+    complex array dL/dRe R + i dL/dIm R ([n_t2][2][n1][n3]), dirs the parameter
+    directions d params / d theta_i (dictionaries with the layout of params)."""
+    p, keep = _params_struct(params)
+    structs = [_params_struct(x) for x in dirs]
+    arr = (heom_params * max(1, len(dirs)))(*[x[0] for x in structs])
+    g, gkeep = _grid_struct(grid)
+    G = np.asarray(dL_dR, dtype=np.complex128)
+    Gi = np.zeros(G.size * 2)
+    Gi[0::2] = np.real(G).ravel()
+    Gi[1::2] = np.imag(G).ravel()
+    out = np.zeros(len(dirs))
+    _check(_lib.heom_response_2d_backward(C.byref(p), model.handle, rho_eq.handle, C.byref(g), _ptr(Gi),
+                                          int(bool(stationary)), float(tol), int(max_steps),
+                                          C.cast(arr, C.c_void_p), len(dirs), float(step), _ptr(out)))
+    return out
+
+
 def response_2d_autograd():
     """torch.autograd.Function computing R(theta) = heom_response_2d on the
     stationary state of the model built from params_at(theta), with the
@@ -580,11 +612,11 @@ def response_2d_autograd():
 
         @staticmethod
         def backward(ctx, grad_R):
-            # torch passes dL/dRe R + i dL/dIm R; the library's weights satisfy
-            # dL = Re sum W dR, i.e. W = conj(grad_R)
-            W = np.conj(grad_R.detach().cpu().numpy())
-            g = heom_response_2d_vjp(ctx.model, ctx.rho, ctx.grid, W, stationary=True, tol=1e-11)
-            gt = heom_params_vjp(ctx.params, ctx.directions, g)
+            # torch passes dL/dRe R + i dL/dIm R, the cotangent convention of
+            # heom_response_2d_backward
+            gt = heom_response_2d_backward(ctx.params, ctx.model, ctx.rho, ctx.grid,
+                                           grad_R.detach().cpu().numpy(), ctx.directions,
+                                           stationary=True, tol=1e-11)
             return torch.from_numpy(gt), None, None, None, None, None
 
     return _Response2D

@@ -133,3 +133,37 @@ def test_batch_errors(instances):
     with pytest.raises(P.heom2dvs.HeomError) as e:
         P.heom_batch_propagate(b, [s3, s1], 1)
     assert e.value.code == P.heom2dvs.HEOM_ERR_STATE
+
+
+def test_batch_six_row_block_class_and_wide_mode_rejected():
+    # FP32 instances with d = 96 (six 16-row blocks: two waves per row block and
+    # the 16-byte operand reads of the multi-instance kernel) next to a d = 80
+    # instance, against the oracle; a mode of 12 kept levels is refused
+    base = w.cfg3()[0]
+    ps = []
+    for keep, depth in (((4, 4, 6), 1), ((4, 4, 6), 2), ((4, 4, 5), 1)):
+        p = dict(base)
+        p["modes"] = [dict(md) for md in base["modes"]]
+        p["depth"] = depth
+        for md, k in zip(p["modes"], keep):
+            md["n_keep"] = k
+        ps.append(p)
+    os_ = [om.build(p) for p in ps]
+    models = [P.heom_model_build(p) for p in ps]
+    states, xs = [], []
+    for i, (m, o) in enumerate(zip(models, os_)):
+        x = w.random_hierarchy(3, len(o.hier), o.d, seed=70 + i, scale_by_depth=0.3 ** o.hier.n.sum(1))
+        s = P.State(m, 3, "fp32")
+        s.upload(x)
+        states.append(s)
+        xs.append(x)
+    P.heom_batch_propagate(P.heom_batch_create(models), states, 2)
+    for o, x, s in zip(os_, xs, states):
+        ref = np.stack([oh.propagate(o, x[t], 2) for t in range(3)])
+        assert _relerr(s.download(), ref) < 1e-5
+    wide = w.cfg2()[0]
+    wide["depth"] = 1
+    wide["modes"][0]["n_keep"] = 12
+    with pytest.raises(P.heom2dvs.HeomError) as e:
+        P.heom_batch_create([P.heom_model_build(wide)])
+    assert e.value.code == P.heom2dvs.HEOM_ERR_PARAM

@@ -211,3 +211,21 @@ def test_autograd_function_matches_oracle(small):
     got = theta.grad.numpy()
     assert abs(loss.item() - f(np.ones(n))) < 1e-8 * max(1.0, abs(loss.item()))
     assert np.max(np.abs(got - ref)) < 1e-5 * np.max(np.abs(ref))
+
+
+def test_response_2d_backward_is_vjp_then_parameter_chain(small):
+    # heom_response_2d_backward(dL/dR) = heom_params_vjp(heom_response_2d_vjp(conj(dL/dR)))
+    params, grid, _, _, rho = small
+    m = P.heom_model_build(params)
+    r = P.State(m, 1, "fp64")
+    r.upload(rho[None])
+    G = _random_W(grid, 5)
+    dirs = w.theta_directions(params)
+    got = P.heom_response_2d_backward(params, m, r, grid, G, dirs, stationary=True, tol=1e-11)
+    g = P.heom_response_2d_vjp(m, r, grid, np.conj(G), stationary=True, tol=1e-11)
+    ref = P.heom_params_vjp(params, dirs, g)
+    assert got.shape == (len(dirs),)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    with pytest.raises(P.heom2dvs.HeomError) as e:
+        P.heom_response_2d_backward(params, m, r, grid, G, [])
+    assert e.value.code == P.heom2dvs.HEOM_ERR_PARAM

@@ -169,6 +169,30 @@ def test_full_size_batched_step_sampled(full_size_refs, kernel):
     assert np.array_equal(got5, got0)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_propagate_sampled_traces_parity(prec, tol):
+    # detection traces tr(mu rho_0) recorded during heom_propagate against the
+    # oracle's propagation sample by sample (n_steps not a multiple of the
+    # sampling interval: the trailing steps are propagated, not sampled)
+    params = _params("cfg2", 2)
+    o = om.build(params)
+    m = P.heom_model_build(params)
+    x = w.random_hierarchy(2, len(o.hier), o.d, seed=8, scale_by_depth=_depth_scale(o))
+    s = P.State(m, 2, prec)
+    s.upload(x)
+    tr = P.heom_propagate(m, s, 23, sample_every=5)
+    assert tr.shape == (5, 2)
+    ref = np.zeros((5, 2), dtype=complex)
+    for b in range(2):
+        y = x[b]
+        for k in range(5):
+            ref[k, b] = np.trace(o.mu @ y[0])
+            y = oh.propagate(o, y, 5 if k < 4 else 3)
+    assert _relerr(tr, ref) < tol
+    assert _relerr(s.download(), np.stack([oh.propagate(o, x[b], 23) for b in range(2)])) < tol
+
+
+
 @pytest.mark.parametrize("which,depth", [("cfg1", None), ("cfg2", 2), ("cfg3", 1), ("paper_scale", 1)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_dipole_and_trace_parity(which, depth, prec):
@@ -446,15 +470,18 @@ def _edge_params(kind):
         p["modes"][0]["n_keep"] = 8
         p["modes"][1]["n_keep"] = 16
         p["modes"][1]["n_basis"] = 20
-    elif kind == "max_mfma32":      # d = 7 x 16 = 112, the largest FP32 matrix-core size
-        p["depth"] = 1
-        p["modes"][0]["n_keep"] = 7
-        p["modes"][1]["n_keep"] = 16
-        p["modes"][1]["n_basis"] = 20
+    elif kind == "max_mfma32":      # d = 7 x 4 x 4 = 112, the largest FP32 matrix-core size
+        p = _params("cfg3", 1)
+        for mode, k in zip(p["modes"], (7, 4, 4)):
+            mode["n_keep"] = k
+    elif kind == "wide_mode":       # a mode of 12 kept levels: beyond the 8 x 8 v_s slot
+        p["depth"] = 2
+        p["modes"][0]["n_keep"] = 12
+        p["modes"][1]["n_keep"] = 5
     return p
 
 
-@pytest.mark.parametrize("kind", ["depth0", "drude_only", "no_bath", "max_d", "max_mfma32"])
+@pytest.mark.parametrize("kind", ["depth0", "drude_only", "no_bath", "max_d", "max_mfma32", "wide_mode"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_rhs_parity_edge_models(kind, prec):
     params = _edge_params(kind)
@@ -464,8 +491,11 @@ def test_rhs_parity_edge_models(kind, prec):
     kernels = ["generic", "mfma"]
     # the matrix-core kernels stage three DP x (DP+1) planes in 160 KB of LDS:
     # d <= 112 in FP32, d <= 80 in FP64
-    if kind == "max_d" or (kind == "max_mfma32" and prec == "fp64"):
+    # (a mode of more than 8 kept levels does not fit the kernels' v_s slot):
+    # those models start on the VALU kernel and refuse the matrix-core ones
+    if kind in ("max_d", "wide_mode") or (kind == "max_mfma32" and prec == "fp64"):
         kernels = ["generic"]
+        assert P.heom_model_get_kernel(m, prec) == "generic"
         with pytest.raises(P.heom2dvs.HeomError) as e:
             P.heom_model_set_kernel(m, prec, "mfma")
         assert e.value.code == P.heom2dvs.HEOM_ERR_PARAM
@@ -610,12 +640,16 @@ def test_batch_with_rate_filtered_instance():
         assert _relerr(s.download(), ref) < 1e-5
 
 
-@pytest.mark.parametrize("keep", [(4, 5), (6, 6), (4, 4, 3)])
+@pytest.mark.parametrize("keep", [(4, 5), (6, 6), (4, 4, 3), (4, 4, 6)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("kernel", ["mfma", "mfma_dyn"])
 def test_rhs_parity_padded_multiple_of_four(keep, prec, kernel):
-    # d = 20, 36, 48: a multiple of four (16-byte rows in global memory and in
-    # the padded LDS planes) but, for 20 and 36, not of 16 (zero-padded tiles)
+    # d = 20, 36, 48, 96: a multiple of four (16-byte rows in global memory and
+    # in the padded LDS planes) but, for 20 and 36, not of 16 (zero-padded
+    # tiles); d = 96 is the six-row-block shape (two waves per row block with
+    # the 16-byte operand reads in FP32), which FP64 runs on the VALU kernel
+    if prec == "fp64" and len(keep) == 3 and np.prod(keep) > 80:
+        pytest.skip("FP64 matrix-core planes hold d <= 80")
     params = _params("cfg3" if len(keep) == 3 else "cfg2", 2)
     for mode, k in zip(params["modes"], keep):
         mode["n_keep"] = k

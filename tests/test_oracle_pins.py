@@ -283,6 +283,102 @@ def test_operators_symmetric_and_counter_term():
     np.testing.assert_allclose(mm.H, np.diag(k + 0.5) + 0.01 * q2, atol=1e-13)
 
 
+def _harmonic_mode(omega, keep, nb=None, **kw):
+    mode = dict(omega=omega, g3=0.0, g4=0.0, V1=1.0, V2=0.0, zeta=0.0, gamma=0.2,
+                mu1=0.0, mu2=0.0, n_basis=nb or keep, n_keep=keep, K=1)
+    mode.update(kw)
+    return mode
+
+
+def _coupled(modes, couplings):
+    return om.build({"modes": modes, "couplings": couplings, "beta": 10.0, "depth": 0,
+                     "decomp": "pade", "dt": 0.1})
+
+
+def _cpl(s, t, g_st=0.0, g_s2t=0.0, g_st2=0.0, mu_st=0.0):
+    return dict(s=s, t=t, g_st=g_st, g_s2t=g_s2t, g_st2=g_st2, mu_st=mu_st)
+
+
+def test_bilinear_coupling_gives_normal_mode_ladder():
+    # Two harmonic modes H = sum_s w_s (p_s^2 + q_s^2)/2 + g q_1 q_2 (Eq.
+    # Potential ss' with only the bilinear term): with x_s = q_s / sqrt(w_s)
+    # this is a pair of oscillators of unit mass with the potential matrix
+    # [[w1^2, g sqrt(w1 w2)], [g sqrt(w1 w2), w2^2]], so the exact spectrum is
+    # sum_k Omega_k (n_k + 1/2) with Omega_k^2 its eigenvalues.  A factor of 2
+    # in the coupling, or the coupling on the wrong operator, moves the levels.
+    w1, w2, g = 1.0, 0.45, 0.05
+    m = _coupled([_harmonic_mode(w1, 24), _harmonic_mode(w2, 24)], [_cpl(0, 1, g_st=g)])
+    Om = np.sqrt(np.linalg.eigvalsh(np.array([[w1 * w1, g * np.sqrt(w1 * w2)],
+                                              [g * np.sqrt(w1 * w2), w2 * w2]])))
+    ladder = np.sort([Om[0] * (a + 0.5) + Om[1] * (b + 0.5) for a in range(8) for b in range(8)])[:8]
+    E = np.linalg.eigvalsh(m.H)[:8]
+    np.testing.assert_allclose(E, ladder, atol=1e-9)
+    # sanity: the uncoupled ladder differs at this accuracy
+    assert np.max(np.abs(np.sort([w1 * (a + .5) + w2 * (b + .5) for a in range(8) for b in range(8)])[:8]
+                         - ladder)) > 1e-4
+
+
+def test_mode_coupling_and_dipole_matrix_elements_by_hand():
+    # Harmonic modes, so the kept basis is the number basis and
+    # <1|q|0> = 1/sqrt(2), <0|q^2|2> = 1/sqrt(2).  Index of |n_0, n_1> with
+    # mode 0 slowest: n_0 * d_1 + n_1.
+    d1 = 4
+    idx = lambda n0, n1: n0 * d1 + n1  # noqa: E731
+    for key, pair, expect in [
+        ("g_s2t", ((0, 1), (2, 0)), 1 / 12),   # (g_s2t/6) <0|q^2|2> <1|q|0>
+        ("g_st2", ((1, 0), (0, 2)), 1 / 12),   # (g_st2/6) <1|q|0> <0|q^2|2>
+        ("g_st", ((1, 1), (0, 0)), 1 / 2),     # g_st <1|q|0> <1|q|0>
+    ]:
+        g = 0.07
+        m = _coupled([_harmonic_mode(1.0, 4, nb=12), _harmonic_mode(0.45, d1, nb=12)], [_cpl(0, 1, **{key: g})])
+        (a0, a1), (b0, b1) = pair
+        assert m.H[idx(a0, a1), idx(b0, b1)] == pytest.approx(g * expect, rel=1e-12), key
+        # the mirrored placement (the term on the other mode) is absent
+        if key != "g_st":
+            assert abs(m.H[idx(a1, a0), idx(b1, b0)]) < 1e-14, key
+    # dipole: (mu2/2) <0|q^2|2> = mu2 / (2 sqrt 2); mu_st <1|q|0>^2 = mu_st / 2
+    mu2, mu_st = 0.3, 0.04
+    m = _coupled([_harmonic_mode(1.0, 4, nb=12, mu2=mu2), _harmonic_mode(0.45, d1, nb=12)],
+                 [_cpl(0, 1, mu_st=mu_st)])
+    assert m.mu[idx(0, 0), idx(2, 0)] == pytest.approx(mu2 / (2 * np.sqrt(2)), rel=1e-12)
+    assert m.mu[idx(0, 0), idx(0, 2)] == pytest.approx(0.0, abs=1e-15)
+    assert m.mu[idx(1, 1), idx(0, 0)] == pytest.approx(mu_st / 2, rel=1e-12)
+    assert m.mu[idx(1, 0), idx(0, 0)] == pytest.approx(0.0, abs=1e-15)   # mu1 = 0
+
+
+def test_three_mode_index_order_and_quanta_from_digits():
+    # (4, 4, 5) product basis, mode 0 slowest: a = 20 n_0 + 5 n_1 + n_2.
+    dims = (4, 4, 5)
+    modes = [_harmonic_mode(1.0, 4, nb=12, mu1=1.0), _harmonic_mode(1.03, 4, nb=12, mu1=1.0),
+             _harmonic_mode(0.44, 5, nb=12, mu1=1.0, mu2=0.2)]
+    g = 0.05
+    m = _coupled(modes, [_cpl(1, 2, g_s2t=g), _cpl(0, 2, g_st=g)])
+    digits = [(a // 20, (a // 5) % 4, a % 5) for a in range(80)]
+    a, b = digits.index((0, 0, 1)), digits.index((0, 2, 0))
+    assert (a, b) == (1, 10)
+    assert m.H[a, b] == pytest.approx(g / 12, rel=1e-12)            # <0_1 1_2|(g/6) q_1^2 q_2|2_1 0_2>
+    assert m.H[digits.index((1, 0, 1)), 0] == pytest.approx(g / 2, rel=1e-12)  # g <1|q|0>_0 <1|q|0>_2
+    # diagonal: the harmonic levels of the three modes
+    for a, (n0, n1, n2) in enumerate(digits):
+        assert m.H[a, a] == pytest.approx(1.0 * (n0 + .5) + 1.03 * (n1 + .5) + 0.44 * (n2 + .5), abs=1e-12)
+    # V_s acts on its own digit only
+    for s in range(3):
+        nz = np.argwhere(np.abs(m.V[s]) > 0)
+        for a, b in nz:
+            da, db = digits[a], digits[b]
+            assert all(da[t] == db[t] for t in range(3) if t != s)
+    # mu_plus keeps exactly the elements that raise the number of quanta
+    N = np.array([sum(dg) for dg in digits])
+    np.testing.assert_array_equal(om.quanta(dims), N)
+    for a in range(80):
+        for b in range(80):
+            want = m.mu[a, b] if N[a] > N[b] else 0.0
+            assert m.mu_plus[a, b] == want
+    np.testing.assert_array_equal(m.mu_minus, m.mu_plus.T)
+    assert m.mu_plus[digits.index((0, 0, 1)), 0] == pytest.approx(1 / np.sqrt(2), rel=1e-12)
+    assert m.mu_plus[0, digits.index((0, 0, 1))] == 0.0
+
+
 # ------------------------------------------------------ RHS and RK4 ---------
 
 def _small_model():
