@@ -376,7 +376,7 @@ def heom_propagate(model, state: State, n_steps: int, adjoint=False, sample_ever
     """n_steps RK4 steps in place; with sample_every > 0 returns the detection
     traces tr(mu rho_0) as a complex array [n_steps // sample_every + 1][n_traj]."""
     if sample_every and sample_every > 0:
-        n_traj = state.shape()[0]
+        n_traj = state.n_traj
         out = np.zeros((int(n_steps) // int(sample_every) + 1) * n_traj * 2)
         _check(_lib.heom_propagate(model.handle, state.handle, int(n_steps), int(bool(adjoint)),
                                    int(sample_every), _ptr(out)))
