@@ -67,9 +67,13 @@ def algorithmic_flops_per_rhs(model):
     return per_ado * model.n_ado + d * d * (2 * n_up + 16 * n_down)
 
 
-def kernel_source_hash():
+KERNEL_FILES = {"generic": ("kernels.hip", "rhs_generic_kernel"), "mfma": ("mfma_rhs.hip", "rhs_mfma_kernel"),
+                "mfma_dyn": ("mfma_rhs.hip", "rhs_mfma_kernel"), "kron": ("kron_rhs.hip", "rhs_kron_kernel")}
+
+
+def kernel_source_hash(kernel="mfma"):
     import hashlib
-    path = os.path.join(ROOT, "paper_2601_20550_amd", "csrc", "mfma_rhs.hip")
+    path = os.path.join(ROOT, "paper_2601_20550_amd", "csrc", KERNEL_FILES[kernel][0])
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
@@ -317,7 +321,7 @@ def main():
                          "scale, 3 x 4 levels, K = 4 Pade, depth 5 (15,504 ADOs), 300 K assumed; "
                          "brownian: cfg3's modes with Brownian baths (complex rate pairs), "
                          "12 terms, depth 5 (6188 ADOs)")
-    ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "mfma", "mfma_dyn"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "mfma", "mfma_dyn", "kron"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path shards into independent "
@@ -388,15 +392,14 @@ def main():
                    "n_ado": m.n_ado, "d": m.d, "trajectories": B},
         "roofline": {"bound": "alu" if kernel == "generic" else "mfma", "achieved": achieved,
                      "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                     "kernel": ("rhs_generic_kernel" if kernel == "generic" else "rhs_mfma_kernel")
-                               + " (fused RHS + RK4 stage)",
+                     "kernel": KERNEL_FILES[kernel][1] + " (fused RHS + RK4 stage)",
                      "avg_launch_ms": avg_launch_s * 1e3, "launches": n_launch},
         "kernel_choice": kernel,
-        "kernel_source": kernel_source_hash(),
+        "kernel_source": kernel_source_hash(kernel),
         "autotune": tune,
     }
 
-    prof = PROFILED_TRAFFIC.get(kernel_source_hash(), {}).get(kernel)
+    prof = PROFILED_TRAFFIC.get(kernel_source_hash(kernel), {}).get(kernel)
     if (prof and prof["batch"] == B
             and prof["precision"] == args.precision and args.depth == 6 and args.workload == "cfg3"):
         line["roofline"]["traffic"] = (prof["read_GB"] + prof["write_GB"]) * 1e9

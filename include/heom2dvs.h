@@ -402,17 +402,30 @@ int heom_batch_response_2d(heom_batch* batch, const heom_state* const* rho_eq, c
  *                         otherwise.
  *   HEOM_KERNEL_MFMA_DYN: the matrix-core kernel with the runtime mode shape
  *                         even where a compile-time one exists.
- * Models start on HEOM_KERNEL_MFMA where it fits the LDS (FP32 d <= 112,
- * FP64 d <= 80) and every mode keeps at most 8 levels (the single-mode
- * operators are staged in 8 x 8 LDS slots), and on HEOM_KERNEL_GENERIC
- * otherwise; heom_model_set_kernel refuses a matrix-core kernel for a model
- * outside these limits (HEOM_ERR_PARAM), and so does heom_batch_create.
- * heom_autotune measures the candidates. */
+ *   HEOM_KERNEL_KRON    : FP32 matrix-core kernel for three-mode models of
+ *                         (4 or 5, 4, 4) levels (d = 64 or 80, e.g. the
+ *                         water-like sym / asym stretch + bend model), one
+ *                         wave per real plane of an output matrix; the mode
+ *                         couplings contract in registers (Kronecker
+ *                         structure of V_s, Eq. sys_interaction).  Such
+ *                         models keep their device matrices in the basis
+ *                         a = 16 a_S + 4 a_M + a_F (slow mode S of 4 or 5
+ *                         levels); state upload / download convert from and
+ *                         to the caller's basis (mode 0 slowest), so the
+ *                         reordering is invisible at this interface.
+ * Models start on HEOM_KERNEL_KRON (FP32) where it applies, otherwise on
+ * HEOM_KERNEL_MFMA where it fits the LDS (FP32 d <= 112, FP64 d <= 80) and
+ * every mode keeps at most 8 levels (the single-mode operators are staged in
+ * 8 x 8 LDS slots), and on HEOM_KERNEL_GENERIC otherwise;
+ * heom_model_set_kernel refuses a kernel outside these limits
+ * (HEOM_ERR_PARAM), and heom_batch_create refuses models outside the
+ * HEOM_KERNEL_MFMA limits.  heom_autotune measures the candidates. */
 typedef enum {
   HEOM_KERNEL_AUTO = 0,
   HEOM_KERNEL_GENERIC = 1,
   HEOM_KERNEL_MFMA = 2,
-  HEOM_KERNEL_MFMA_DYN = 3
+  HEOM_KERNEL_MFMA_DYN = 3,
+  HEOM_KERNEL_KRON = 4
 } heom_kernel;
 int heom_model_set_kernel(heom_model* model, int precision, int kernel);
 int heom_model_get_kernel(const heom_model* model, int precision, int* kernel_out);
@@ -437,10 +450,13 @@ int heom_model_set_graph_steps(heom_model* model, int steps);
  * turns it off (default).  The callback must not call into this library. */
 typedef void (*heom_progress_fn)(const char* phase, long long done, long long total, void* ctx);
 int heom_model_set_progress(heom_model* model, heom_progress_fn fn, void* ctx, int every_steps);
-/* Times every kernel variant on a scratch batch of n_traj trajectories in
- * the given precision (reps RK4 steps each) and keeps the fastest for this
- * model and precision.  ms_out (may be NULL) receives the measured time per
- * RK4 step of each variant, indexed by heom_kernel (entry 0 unused). */
+/* Times every kernel variant that applies to the model (variants that would
+ * run the same code are timed once) on a scratch batch of n_traj
+ * trajectories in the given precision (one warm-up step, then reps RK4
+ * steps each) and keeps the fastest for this model and precision.  ms_out
+ * (may be NULL; HEOM_KERNEL_KRON + 1 entries) receives the measured time per
+ * RK4 step indexed by heom_kernel, NaN for variants not timed.  The
+ * previous choice is kept when an error occurs. */
 int heom_autotune(heom_model* model, int n_traj, int precision, int reps, int* kernel_out,
                   double* ms_out);
 

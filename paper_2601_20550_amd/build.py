@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libheom2dvs.so")
 
-SOURCES = ["kernels.hip", "mfma_rhs.hip", "grad.hip", "capi.hip", "model_build.cpp"]
+SOURCES = ["kernels.hip", "mfma_rhs.hip", "kron_rhs.hip", "grad.hip", "capi.hip", "model_build.cpp"]
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU ops.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -133,14 +133,25 @@ struct heom_model {
   // device copies
   DevBuf H64, H32, v64, v32, g64, g32, gi64, gi32, mu64[3];
   DevBuf Hp64, Hp32;  // H zero-padded to a multiple of 16 (matrix-core kernel)
+  // Device basis: the product basis reordered so that three-mode models of
+  // the (S; 4, 4) structure read a = 16 a_S + 4 a_M + a_F (the layout of the
+  // HEOM_KERNEL_KRON kernel); every device operator and state is in it, and
+  // states are permuted at upload / download.  perm[device index] = index
+  // in the caller's basis (mode 0 slowest); empty when the two coincide.
+  std::vector<int> perm;
+  int dstrides[4] = {1, 1, 1, 1};       // strides of the modes in the device basis
+  bool kron = false;                    // HEOM_KERNEL_KRON available
+  heom::KronArgs kargs[2];              // forward / transposed tables
+  std::vector<double> mu_dev;           // mu in the device basis (host copy)
+  std::vector<int> quanta_dev;          // N(a) in the device basis
   int kernel[2] = {HEOM_KERNEL_MFMA, HEOM_KERNEL_MFMA};  // per precision
   DevBuf nb_ptr[2], nb_idx[2], nb_a64[2], nb_a32[2];
   DevBuf nb_tj, ado_n;  // forward-table (term, count) pairs and ADO indices (gradient kernels)
   heom::GradOps gops{};
   heom::DevOps<double> ops64[2];
   heom::DevOps<float> ops32[2];
-  // scratch: two hierarchy-sized work buffers per precision, grown on demand
-  DevBuf scratch[2];
+  // two hierarchy-sized work buffers (RK4 stages, dipole results), grown on demand
+  DevBuf work[2];
   DevBuf red_partial, red_result;
   // captured RK4 step sequences (launch-bound models): graph_steps RK4 steps
   // per graph, 0 = off; graphs are captured on cap_stream and replayed on stream
@@ -208,6 +219,49 @@ heom_params copy_check(const heom_params* p) {
   return *p;
 }
 
+// Chooses the device basis (see heom_model::perm) and returns the d x d
+// operator A (caller's basis) in it.
+void choose_device_basis(heom_model* m) {
+  const auto& hm = m->hm;
+  int roles[3];
+  m->perm.clear();
+  for (int s = 0; s < 4; ++s) m->dstrides[s] = hm.strides[s];
+  m->kron = heom::kron_roles(hm.d, hm.n_modes, hm.dims, roles);
+  if (!m->kron) return;
+  const int S = roles[0], M = roles[1], F = roles[2];
+  m->dstrides[S] = 16;
+  m->dstrides[M] = 4;
+  m->dstrides[F] = 1;
+  m->perm.resize(hm.d);
+  for (int a = 0; a < hm.d; ++a) {
+    const int aS = a / 16, aM = (a / 4) % 4, aF = a % 4;
+    m->perm[a] = aS * hm.strides[S] + aM * hm.strides[M] + aF * hm.strides[F];
+  }
+  bool identity = true;
+  for (int a = 0; a < hm.d; ++a) identity = identity && m->perm[a] == a;
+  if (identity) m->perm.clear();
+}
+
+std::vector<double> to_device_basis(const heom_model* m, const std::vector<double>& A) {
+  if (m->perm.empty()) return A;
+  const int d = m->hm.d;
+  std::vector<double> B(A.size());
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b)
+      B[static_cast<size_t>(a) * d + b] = A[static_cast<size_t>(m->perm[a]) * d + m->perm[b]];
+  return B;
+}
+
+// d x d array in the device basis -> caller's basis, in place
+void to_user_basis(const heom_model* m, double* A) {
+  if (m->perm.empty()) return;
+  const int d = m->hm.d;
+  std::vector<double> B(A, A + static_cast<size_t>(d) * d);
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b)
+      A[static_cast<size_t>(m->perm[a]) * d + m->perm[b]] = B[static_cast<size_t>(a) * d + b];
+}
+
 void upload_model(heom_model* m) {
   const auto& hm = m->hm;
   hipStream_t st = m->stream;
@@ -216,8 +270,13 @@ void upload_model(heom_model* m) {
     tmp.assign(v.begin(), v.end());
     return upload_vec(tmp, st);
   };
-  m->H64 = upload_vec(hm.H, st);
-  m->H32 = f32(hm.H);
+  choose_device_basis(m);
+  const std::vector<double> Hd = to_device_basis(m, hm.H);
+  m->mu_dev = to_device_basis(m, hm.mu);
+  m->quanta_dev.resize(hm.d);
+  for (int a = 0; a < hm.d; ++a) m->quanta_dev[a] = hm.quanta[m->perm.empty() ? a : m->perm[a]];
+  m->H64 = upload_vec(Hd, st);
+  m->H32 = f32(Hd);
   std::vector<double> vpack;
   int v_off[4] = {0, 0, 0, 0};
   for (int s = 0; s < hm.n_modes; ++s) {
@@ -232,9 +291,9 @@ void upload_model(heom_model* m) {
     m->gi64 = upload_vec(hm.gamma_sum_im, st);
     m->gi32 = f32(hm.gamma_sum_im);
   }
-  m->mu64[HEOM_OP_MU] = upload_vec(hm.mu, st);
-  m->mu64[HEOM_OP_MU_PLUS] = upload_vec(hm.mu_plus, st);
-  m->mu64[HEOM_OP_MU_MINUS] = upload_vec(hm.mu_minus, st);
+  m->mu64[HEOM_OP_MU] = upload_vec(m->mu_dev, st);
+  m->mu64[HEOM_OP_MU_PLUS] = upload_vec(to_device_basis(m, hm.mu_plus), st);
+  m->mu64[HEOM_OP_MU_MINUS] = upload_vec(to_device_basis(m, hm.mu_minus), st);
   for (int dir = 0; dir < 2; ++dir) {
     const heom::Neighbours& nb = dir == 0 ? hm.fwd : hm.adj;
     m->nb_ptr[dir] = upload_vec(nb.ptr, st);
@@ -261,7 +320,7 @@ void upload_model(heom_model* m) {
       for (int s = 0; s < 4; ++s) {
         op.v_off[s] = v_off[s];
         op.dims[s] = hm.dims[s];
-        op.strides[s] = hm.strides[s];
+        op.strides[s] = m->dstrides[s];
       }
       op.n_modes = hm.n_modes;
       op.d = hm.d;
@@ -274,7 +333,7 @@ void upload_model(heom_model* m) {
     const int d = hm.d, DP = 16 * ((d + 15) / 16);
     std::vector<double> hp(static_cast<size_t>(DP) * DP, 0.0);
     for (int a = 0; a < d; ++a)
-      for (int c = 0; c < d; ++c) hp[static_cast<size_t>(a) * DP + c] = hm.H[static_cast<size_t>(a) * d + c];
+      for (int c = 0; c < d; ++c) hp[static_cast<size_t>(a) * DP + c] = Hd[static_cast<size_t>(a) * d + c];
     m->Hp64 = upload_vec(hp, st);
     m->Hp32 = f32(hp);
     if (!heom::mfma_supported<double>(d, hm.n_modes, hm.dims)) m->kernel[HEOM_FP64] = HEOM_KERNEL_GENERIC;
@@ -293,12 +352,38 @@ void upload_model(heom_model* m) {
     for (int s = 0; s < 4; ++s) {
       g.v_off[s] = v_off[s];
       g.dims[s] = hm.dims[s];
-      g.strides[s] = hm.strides[s];
+      g.strides[s] = m->dstrides[s];
     }
     g.n_modes = hm.n_modes;
     g.d = hm.d;
     g.n_ado = hm.n_ado;
     g.n_terms = hm.n_terms;
+  }
+  if (m->kron) {
+    int roles[3];
+    heom::kron_roles(hm.d, hm.n_modes, hm.dims, roles);
+    for (int dir = 0; dir < 2; ++dir) {
+      heom::KronArgs& k = m->kargs[dir];
+      const auto& op = m->ops32[dir];
+      k.H = op.H;
+      k.gamma = op.gamma;
+      k.gamma_im = op.gamma_im;
+      k.nb_ptr = op.nb_ptr;
+      k.nb_idx = op.nb_idx;
+      k.nb_a = op.nb_a;
+      k.n_modes = hm.n_modes;
+      k.n_ado = hm.n_ado;
+      k.mode_S = roles[0];
+      k.mode_M = roles[1];
+      k.mode_F = roles[2];
+      for (int e = 0; e < 64; ++e) k.vS[e] = 0.0f;
+      for (size_t e = 0; e < hm.v[roles[0]].size(); ++e) k.vS[e] = static_cast<float>(hm.v[roles[0]][e]);
+      for (int e = 0; e < 16; ++e) {
+        k.vM[e] = static_cast<float>(hm.v[roles[1]][e]);
+        k.vF[e] = static_cast<float>(hm.v[roles[2]][e]);
+      }
+    }
+    m->kernel[HEOM_FP32] = HEOM_KERNEL_KRON;
   }
   m->red_result = DevBuf(sizeof(double) * 4);
   m->has_device = true;
@@ -340,7 +425,13 @@ void launch_stage(heom_model* m, bool adjoint, const T* in, const T* y, T* out, 
   const int k = m->kernel[prec_of<T>()];
   if (k == HEOM_KERNEL_GENERIC)
     heom::launch_rhs<T>(op, in, y, out, coef, n_traj, m->stream);
-  else
+  else if constexpr (std::is_same<T, float>::value) {
+    if (k == HEOM_KERNEL_KRON)
+      heom::launch_rhs_kron(m->kargs[adjoint ? 1 : 0], m->hm.d, in, y, out, coef, n_traj, m->stream);
+    else
+      heom::launch_rhs_mfma<T>(op, padded_H<T>(m), in, y, out, coef, n_traj, k == HEOM_KERNEL_MFMA_DYN ? 1 : 0,
+                               m->stream);
+  } else
     heom::launch_rhs_mfma<T>(op, padded_H<T>(m), in, y, out, coef, n_traj, k == HEOM_KERNEL_MFMA_DYN ? 1 : 0,
                              m->stream);
 }
@@ -361,15 +452,15 @@ void stage(heom_model* m, bool adjoint, const T* in, const T* y, T* out, double 
 }
 
 template <typename T>
-T* scratch(heom_model* m, int slot, long long elems) {
+T* work_buffer(heom_model* m, int slot, long long elems) {
   size_t bytes = static_cast<size_t>(elems) * sizeof(T);
-  if (m->scratch[slot].bytes < bytes) {
-    hip_check(hipStreamSynchronize(m->stream), "sync before scratch growth");
+  if (m->work[slot].bytes < bytes) {
+    hip_check(hipStreamSynchronize(m->stream), "sync before work buffer growth");
     m->clear_graphs();
-    m->scratch[slot] = DevBuf();
-    m->scratch[slot] = DevBuf(bytes);
+    m->work[slot] = DevBuf();
+    m->work[slot] = DevBuf(bytes);
   }
-  return m->scratch[slot].as<T>();
+  return m->work[slot].as<T>();
 }
 
 // n_steps RK4 steps in place on y (n_traj trajectories), with work buffers
@@ -440,11 +531,11 @@ void rk4_steps(heom_model* m, T* y, T* w1, T* w2, int n_traj, int n_steps, bool 
 }
 
 template <typename T>
-void rk4_steps_scratch(heom_model* m, T* y, int n_traj, int n_steps, bool adjoint) {
+void rk4_steps_ws(heom_model* m, T* y, int n_traj, int n_steps, bool adjoint) {
   if (n_steps <= 0) return;
   const long long elems = static_cast<long long>(n_traj) * m->traj_elems();
-  T* w1 = scratch<T>(m, 0, elems);
-  T* w2 = scratch<T>(m, 1, elems);
+  T* w1 = work_buffer<T>(m, 0, elems);
+  T* w2 = work_buffer<T>(m, 1, elems);
   rk4_steps<T>(m, y, w1, w2, n_traj, n_steps, adjoint);
 }
 
@@ -497,11 +588,11 @@ double absmax(heom_model* m, const T* x, long long n_mats) {
   return r;
 }
 
-// L(x) into scratch slot 0, then max |.|
+// L(x) into work buffer 0, then max |.|
 template <typename T>
 double residual_of(heom_model* m, const T* x, int n_traj) {
   const long long elems = static_cast<long long>(n_traj) * m->traj_elems();
-  T* w = scratch<T>(m, 0, elems);
+  T* w = work_buffer<T>(m, 0, elems);
   launch_stage<T>(m, false, x, nullptr, w, 1.0, n_traj);
   return absmax<T>(m, w, static_cast<long long>(n_traj) * m->hm.n_ado);
 }
@@ -518,18 +609,18 @@ template <typename T>
 void propagate_sampled(heom_model* m, heom_state* s, int n_steps, bool adjoint, int sample_every, double* trace_out) {
   T* y = s->buf.as<T>();
   if (sample_every <= 0 || !trace_out) {
-    rk4_steps_scratch<T>(m, y, s->n_traj, n_steps, adjoint);
+    rk4_steps_ws<T>(m, y, s->n_traj, n_steps, adjoint);
   } else {
     // tr(mu rho_0) of every trajectory at steps 0, sample_every, ... <= n_steps
     const int n_samples = n_steps / sample_every + 1;
     DevBuf tr(static_cast<size_t>(n_samples) * s->n_traj * 2 * sizeof(double));
     for (int k = 0; k < n_samples; ++k) {
-      if (k > 0) rk4_steps_scratch<T>(m, y, s->n_traj, sample_every, adjoint);
+      if (k > 0) rk4_steps_ws<T>(m, y, s->n_traj, sample_every, adjoint);
       heom::launch_trace<T>(m->mu64[HEOM_OP_MU].as<double>(), y, m->hm.d, m->traj_elems(), s->n_traj,
                             tr.as<double>() + static_cast<size_t>(k) * s->n_traj * 2, 1, m->stream);
     }
     const int rest = n_steps - (n_samples - 1) * sample_every;
-    if (rest > 0) rk4_steps_scratch<T>(m, y, s->n_traj, rest, adjoint);
+    if (rest > 0) rk4_steps_ws<T>(m, y, s->n_traj, rest, adjoint);
     hip_check(hipMemcpyAsync(trace_out, tr.p, tr.bytes, hipMemcpyDeviceToHost, m->stream), "copy");
     hip_check(hipStreamSynchronize(m->stream), "sync");
   }
@@ -580,7 +671,7 @@ void linear_response_impl(heom_model* m, const heom_state* rho_eq, int n, int sp
   commute_from64<T>(m, HEOM_OP_MU, 0, rho_eq->buf.as<double>(), X.as<T>(), m->hm.n_ado, tmp.as<double>());
   DevBuf out(static_cast<size_t>(n) * 2 * sizeof(double));
   for (int k = 0; k < n; ++k) {
-    if (k) rk4_steps_scratch<T>(m, X.as<T>(), 1, sps, false);
+    if (k) rk4_steps_ws<T>(m, X.as<T>(), 1, sps, false);
     heom::launch_trace<T>(m->mu64[HEOM_OP_MU].as<double>(), X.as<T>(), d, te, 1, out.as<double>() + 2 * k, 1,
                           m->stream);
   }
@@ -603,7 +694,7 @@ void t1_snapshots(heom_model* m, const heom_state* rho_eq, int D1, int D2, int n
   DevBuf tmp(static_cast<size_t>(te) * sizeof(double));
   commute_from64<T>(m, D1, 0, rho_eq->buf.as<double>(), X.as<T>(), n_mats, tmp.as<double>());
   for (int j = 0; j < n1; ++j) {
-    if (j) rk4_steps_scratch<T>(m, X.as<T>(), 1, sps, false);
+    if (j) rk4_steps_ws<T>(m, X.as<T>(), 1, sps, false);
     heom::launch_commutator<T>(m->mu64[D2].as<double>(), 0, X.as<T>(), snap + j * te, m->hm.d, n_mats,
                                m->stream);
   }
@@ -676,12 +767,12 @@ void response_adjoint(heom_model* m, const heom_state* rho_eq, const heom_grid& 
   {
     std::vector<double> h(static_cast<size_t>(te), 0.0);
     for (int a = 0; a < d; ++a)
-      for (int c = 0; c < d; ++c) h[static_cast<size_t>(a) * d + c] = m->hm.mu[static_cast<size_t>(c) * d + a];
+      for (int c = 0; c < d; ++c) h[static_cast<size_t>(a) * d + c] = m->mu_dev[static_cast<size_t>(c) * d + a];
     DevBuf l64 = upload_vec(h, m->stream);
     DevBuf l(tb);
     heom::launch_convert<double, T>(l64.as<double>(), l.as<T>(), te, m->stream);
     for (int k = 0; k < n3; ++k) {
-      if (k) rk4_steps_scratch<T>(m, l.as<T>(), 1, sps, true);
+      if (k) rk4_steps_ws<T>(m, l.as<T>(), 1, sps, true);
       if (one_d3)
         heom::launch_commutator<T>(m->mu64[ops[2]].as<double>(), 1, l.as<T>(), Psi.as<T>() + k * te, d,
                                    m->hm.n_ado, m->stream);
@@ -864,7 +955,7 @@ void batch_response_adjoint(heom_batch* b, const heom_state* const* rho_eq, cons
     const int d = m->hm.d;
     std::vector<double> h(static_cast<size_t>(te[i]), 0.0);
     for (int a = 0; a < d; ++a)
-      for (int c = 0; c < d; ++c) h[static_cast<size_t>(a) * d + c] = m->hm.mu[static_cast<size_t>(c) * d + a];
+      for (int c = 0; c < d; ++c) h[static_cast<size_t>(a) * d + c] = m->mu_dev[static_cast<size_t>(c) * d + a];
     DevBuf l64 = upload_vec(h, b->stream);
     l[i] = DevBuf(static_cast<size_t>(te[i]) * sizeof(T));
     heom::launch_convert<double, T>(l64.as<double>(), l[i].as<T>(), te[i], b->stream);
@@ -974,7 +1065,7 @@ struct Krylov {
   // w = (I - Phi^m) v
   void apply(const double* v, double* w) {
     copy(v, tmp.as<double>());
-    rk4_steps_scratch<double>(m, tmp.as<double>(), 1, msteps, adjoint);
+    rk4_steps_ws<double>(m, tmp.as<double>(), 1, msteps, adjoint);
     copy(v, w);
     axpy(-1.0, tmp.as<double>(), w);
     steps_done += msteps;
@@ -1231,12 +1322,12 @@ void response_vjp(heom_model* m, const heom_state* rho_eq, const heom_grid& gr, 
   {
     std::vector<double> h(static_cast<size_t>(te), 0.0);
     for (int a = 0; a < d; ++a)
-      for (int c = 0; c < d; ++c) h[static_cast<size_t>(a) * d + c] = m->hm.mu[static_cast<size_t>(c) * d + a];
+      for (int c = 0; c < d; ++c) h[static_cast<size_t>(a) * d + c] = m->mu_dev[static_cast<size_t>(c) * d + a];
     hip_check(hipMemcpyAsync(Lk.p, h.data(), te * sizeof(double), hipMemcpyHostToDevice, st), "upload");
     hip_check(hipStreamSynchronize(st), "sync");
     for (int k = 1; k < n3; ++k) {
       copy_dev(Lk.as<double>() + k * te, Lk.as<double>() + (k - 1) * te, te, st);
-      rk4_steps_scratch<double>(m, Lk.as<double>() + k * te, 1, sps, true);
+      rk4_steps_ws<double>(m, Lk.as<double>() + k * te, 1, sps, true);
     }
     heom::launch_commutator<double>(m->mu64[HEOM_OP_MU_PLUS].as<double>(), 1, Lk.as<double>(), Psi.as<double>(), d,
                                     static_cast<long long>(n3) * n_ado, st);
@@ -1268,7 +1359,7 @@ void response_vjp(heom_model* m, const heom_state* rho_eq, const heom_grid& gr, 
     heom::launch_commutator<double>(m->mu64[D1].as<double>(), 0, rho, Xc.as<double>(), d, n_ado, st);
     for (int j = 1; j < n1; ++j) {
       copy_dev(Xc.as<double>() + j * te, Xc.as<double>() + (j - 1) * te, te, st);
-      rk4_steps_scratch<double>(m, Xc.as<double>() + j * te, 1, sps, false);
+      rk4_steps_ws<double>(m, Xc.as<double>() + j * te, 1, sps, false);
     }
     DevBuf Y(static_cast<size_t>(nc) * te * sizeof(double)), A(static_cast<size_t>(nc) * te * sizeof(double));
     DevBuf CK(static_cast<size_t>(std::max(nbd - 1, 1)) * nc * te * sizeof(double));
@@ -1292,7 +1383,7 @@ void response_vjp(heom_model* m, const heom_state* rho_eq, const heom_grid& gr, 
           combine(g, Y.as<double>(), te, c, phi.as<double>(), te, n3, cfd.as<double>(), 1, 1);
           hip_check(hipStreamSynchronize(st), "sync");
         }
-        if (i + 1 < nbd) rk4_steps_scratch<double>(m, Y.as<double>(), c, bnd[i + 1] - bnd[i], false);
+        if (i + 1 < nbd) rk4_steps_ws<double>(m, Y.as<double>(), c, bnd[i + 1] - bnd[i], false);
       }
       // backward over t2: sources sigma_q = sum_k (-i W) Psi_k at t2_q
       zero_dev(A, st);
@@ -1378,7 +1469,7 @@ void response_vjp(heom_model* m, const heom_state* rho_eq, const heom_grid& gr, 
       K.steps_total = static_cast<long long>(std::max(1, max_steps / M)) * M;
       K.zero(bsum.as<double>());
       for (int n = 0; n < M; ++n) {
-        if (n) rk4_steps_scratch<double>(m, grho.as<double>(), 1, 1, true);
+        if (n) rk4_steps_ws<double>(m, grho.as<double>(), 1, 1, true);
         K.axpy(g.h, grho.as<double>(), bsum.as<double>());
       }
       K.zero(kd.as<double>());
@@ -1410,12 +1501,14 @@ void response_vjp(heom_model* m, const heom_state* rho_eq, const heom_grid& gr, 
   hip_check(hipMemcpyAsync(out->dc, g.gc.p, g.gc.bytes, hipMemcpyDeviceToHost, st), "copy");
   hip_check(hipMemcpyAsync(out->dnu, g.gnu.p, g.gnu.bytes, hipMemcpyDeviceToHost, st), "copy");
   hip_check(hipStreamSynchronize(st), "sync");
-  const auto& Nq = m->hm.quanta;
+  const auto& Nq = m->quanta_dev;
   for (long long i = 0; i < dd; ++i) out->dH[i] = hr[i];
   for (int a = 0; a < d; ++a)
     for (int b = 0; b < d; ++b) {
       if (Nq[a] > Nq[b]) out->dmu[a * d + b] += hr[dd + a * d + b] + hr[2 * dd + static_cast<long long>(b) * d + a];
     }
+  to_user_basis(m, out->dH);
+  to_user_basis(m, out->dmu);
   auto finite = [](const double* x, size_t n) {
     for (size_t i = 0; i < n; ++i)
       if (!std::isfinite(x[i])) return false;
@@ -1604,6 +1697,20 @@ int heom_state_shape(const heom_state* s, int* n_traj, int* precision) {
   });
 }
 
+namespace {
+// element e = a d + b of a matrix in the device basis -> its index in the
+// caller's basis
+std::vector<long long> basis_map(const heom_model* m) {
+  const int d = m->hm.d;
+  std::vector<long long> e(static_cast<size_t>(d) * d);
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b)
+      e[static_cast<size_t>(a) * d + b] =
+          m->perm.empty() ? static_cast<long long>(a) * d + b : static_cast<long long>(m->perm[a]) * d + m->perm[b];
+  return e;
+}
+}  // namespace
+
 int heom_state_upload_range(heom_state* s, int first, int count, const double* host) {
   return guarded([&] {
     if (!s || !host) throw HeomError(HEOM_ERR_PARAM, "null argument");
@@ -1616,10 +1723,12 @@ int heom_state_upload_range(heom_state* s, int first, int count, const double* h
     auto go = [&](auto* tag) {
       using T = std::remove_pointer_t<decltype(tag)>;
       std::vector<T> t(static_cast<size_t>(n_mats * 2 * dd));
+      const std::vector<long long> src = basis_map(m);
       for (long long q = 0; q < n_mats; ++q)
         for (long long e = 0; e < dd; ++e) {
-          t[q * 2 * dd + e] = static_cast<T>(host[2 * (q * dd + e)]);
-          t[q * 2 * dd + dd + e] = static_cast<T>(host[2 * (q * dd + e) + 1]);
+          const long long u = q * dd + src[e];
+          t[q * 2 * dd + e] = static_cast<T>(host[2 * u]);
+          t[q * 2 * dd + dd + e] = static_cast<T>(host[2 * u + 1]);
         }
       hip_check(hipMemcpyAsync(s->buf.as<T>() + off, t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice,
                                m->stream), "upload");
@@ -1645,10 +1754,12 @@ int heom_state_download_range(const heom_state* s, int first, int count, double*
       hip_check(hipMemcpyAsync(t.data(), s->buf.as<T>() + off, t.size() * sizeof(T), hipMemcpyDeviceToHost,
                                m->stream), "download");
       hip_check(hipStreamSynchronize(m->stream), "sync");
+      const std::vector<long long> src = basis_map(m);
       for (long long q = 0; q < n_mats; ++q)
         for (long long e = 0; e < dd; ++e) {
-          host[2 * (q * dd + e)] = static_cast<double>(t[q * 2 * dd + e]);
-          host[2 * (q * dd + e) + 1] = static_cast<double>(t[q * 2 * dd + dd + e]);
+          const long long u = q * dd + src[e];
+          host[2 * u] = static_cast<double>(t[q * 2 * dd + e]);
+          host[2 * u + 1] = static_cast<double>(t[q * 2 * dd + dd + e]);
         }
     };
     if (s->precision == HEOM_FP64) go(static_cast<double*>(nullptr));
@@ -1739,12 +1850,12 @@ int heom_apply_dipole(heom_model* m, heom_state* s, int op, int transpose) {
     const long long n_mats = static_cast<long long>(s->n_traj) * m->hm.n_ado;
     const long long n = s->n_elems();
     if (s->precision == HEOM_FP64) {
-      double* w = scratch<double>(m, 0, n);
+      double* w = work_buffer<double>(m, 0, n);
       heom::launch_commutator<double>(m->mu64[op].as<double>(), transpose, s->buf.as<double>(), w, m->hm.d,
                                       n_mats, m->stream);
       heom::launch_convert<double, double>(w, s->buf.as<double>(), n, m->stream);
     } else {
-      float* w = scratch<float>(m, 0, n);
+      float* w = work_buffer<float>(m, 0, n);
       heom::launch_commutator<float>(m->mu64[op].as<double>(), transpose, s->buf.as<float>(), w, m->hm.d, n_mats,
                                      m->stream);
       heom::launch_convert<float, float>(w, s->buf.as<float>(), n, m->stream);
@@ -1864,7 +1975,7 @@ int heom_equilibrate_krylov(heom_model* m, double tol, int pre_steps, int steps_
       throw HeomError(HEOM_ERR_PARAM, "bad Krylov parameters");
     auto s = new_state(m, 1, HEOM_FP64);
     heom::launch_set_ground<double>(s->buf.as<double>(), m->traj_elems(), 1, s->n_elems(), m->stream);
-    rk4_steps_scratch<double>(m, s->buf.as<double>(), 1, pre_steps, false);
+    rk4_steps_ws<double>(m, s->buf.as<double>(), 1, pre_steps, false);
     int used = 0;
     double res = 0.0;
     krylov_refine(m, s->buf.as<double>(), tol, steps_per_apply, restart, max_applies, &used, &res);
@@ -2234,10 +2345,15 @@ int heom_model_set_kernel(heom_model* m, int precision, int kernel) {
   return guarded([&] {
     require_device(m);
     if (precision != HEOM_FP64 && precision != HEOM_FP32) throw HeomError(HEOM_ERR_PARAM, "bad precision");
-    if (kernel < HEOM_KERNEL_AUTO || kernel > HEOM_KERNEL_MFMA_DYN) throw HeomError(HEOM_ERR_PARAM, "bad kernel");
-    const bool ok = precision == HEOM_FP64 ? heom::mfma_supported<double>(m->hm.d, m->hm.n_modes, m->hm.dims) : heom::mfma_supported<float>(m->hm.d, m->hm.n_modes, m->hm.dims);
-    if (kernel == HEOM_KERNEL_AUTO) kernel = ok ? HEOM_KERNEL_MFMA : HEOM_KERNEL_GENERIC;
-    if (kernel != HEOM_KERNEL_GENERIC && !ok) throw HeomError(HEOM_ERR_PARAM, "matrix-core kernel unsupported for this d");
+    if (kernel < HEOM_KERNEL_AUTO || kernel > HEOM_KERNEL_KRON) throw HeomError(HEOM_ERR_PARAM, "bad kernel");
+    const bool ok = precision == HEOM_FP64 ? heom::mfma_supported<double>(m->hm.d, m->hm.n_modes, m->hm.dims)
+                                           : heom::mfma_supported<float>(m->hm.d, m->hm.n_modes, m->hm.dims);
+    if (kernel == HEOM_KERNEL_AUTO)
+      kernel = (precision == HEOM_FP32 && m->kron) ? HEOM_KERNEL_KRON : ok ? HEOM_KERNEL_MFMA : HEOM_KERNEL_GENERIC;
+    if (kernel == HEOM_KERNEL_KRON && (precision != HEOM_FP32 || !m->kron))
+      throw HeomError(HEOM_ERR_PARAM, "the (S;4,4) matrix-core kernel needs FP32 and three modes of (4|5, 4, 4) levels");
+    if ((kernel == HEOM_KERNEL_MFMA || kernel == HEOM_KERNEL_MFMA_DYN) && !ok)
+      throw HeomError(HEOM_ERR_PARAM, "matrix-core kernel unsupported for this d");
     m->kernel[precision] = kernel;
     m->clear_graphs();
   });
@@ -2276,34 +2392,52 @@ int heom_autotune(heom_model* m, int n_traj, int precision, int reps, int* kerne
     if (n_traj < 1 || reps < 1) throw HeomError(HEOM_ERR_PARAM, "bad autotune sizes");
     if (precision != HEOM_FP64 && precision != HEOM_FP32) throw HeomError(HEOM_ERR_PARAM, "bad precision");
     auto s = new_state(m, n_traj, precision);
-    hipEvent_t e0, e1;
-    hip_check(hipEventCreate(&e0), "event");
-    hip_check(hipEventCreate(&e1), "event");
-    const int saved = m->kernel[precision];
-    const bool saved_timing = m->timing;
+    // restores the kernel choice and timing flag and frees the events on every exit
+    struct Guard {
+      heom_model* m;
+      int prec, kernel;
+      bool timing;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      ~Guard() {
+        m->kernel[prec] = kernel;
+        m->timing = timing;
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+      }
+    } guard{m, precision, m->kernel[precision], m->timing};
+    hip_check(hipEventCreate(&guard.e0), "event");
+    hip_check(hipEventCreate(&guard.e1), "event");
     m->timing = false;
-    int best = saved;
+    const bool ok = precision == HEOM_FP64 ? heom::mfma_supported<double>(m->hm.d, m->hm.n_modes, m->hm.dims)
+                                           : heom::mfma_supported<float>(m->hm.d, m->hm.n_modes, m->hm.dims);
+    const bool distinct_dyn = precision == HEOM_FP64 ? heom::mfma_static_shape<double>(m->ops64[0])
+                                                     : heom::mfma_static_shape<float>(m->ops32[0]);
+    std::vector<int> cand = {HEOM_KERNEL_GENERIC};
+    if (ok) cand.push_back(HEOM_KERNEL_MFMA);
+    if (ok && distinct_dyn) cand.push_back(HEOM_KERNEL_MFMA_DYN);
+    if (precision == HEOM_FP32 && m->kron) cand.push_back(HEOM_KERNEL_KRON);
+    if (ms_out)
+      for (int k = 0; k <= HEOM_KERNEL_KRON; ++k) ms_out[k] = std::nan("");
+    int best = guard.kernel;
     double best_ms = 1e300;
-    const bool ok = precision == HEOM_FP64 ? heom::mfma_supported<double>(m->hm.d, m->hm.n_modes, m->hm.dims) : heom::mfma_supported<float>(m->hm.d, m->hm.n_modes, m->hm.dims);
-    for (int k = HEOM_KERNEL_GENERIC; k <= HEOM_KERNEL_MFMA_DYN; ++k) {
-      if (k != HEOM_KERNEL_GENERIC && !ok) continue;
+    for (int k : cand) {
       m->kernel[precision] = k;
       auto run = [&](int steps) {
         if (precision == HEOM_FP64) {
           heom::launch_set_ground<double>(s->buf.as<double>(), m->traj_elems(), n_traj, s->n_elems(), m->stream);
-          rk4_steps_scratch<double>(m, s->buf.as<double>(), n_traj, steps, false);
+          rk4_steps_ws<double>(m, s->buf.as<double>(), n_traj, steps, false);
         } else {
           heom::launch_set_ground<float>(s->buf.as<float>(), m->traj_elems(), n_traj, s->n_elems(), m->stream);
-          rk4_steps_scratch<float>(m, s->buf.as<float>(), n_traj, steps, false);
+          rk4_steps_ws<float>(m, s->buf.as<float>(), n_traj, steps, false);
         }
       };
       run(1);  // warm-up (first launch configures the kernel)
-      hip_check(hipEventRecord(e0, m->stream), "event");
+      hip_check(hipEventRecord(guard.e0, m->stream), "event");
       run(reps);
-      hip_check(hipEventRecord(e1, m->stream), "event");
-      hip_check(hipEventSynchronize(e1), "event sync");
+      hip_check(hipEventRecord(guard.e1, m->stream), "event");
+      hip_check(hipEventSynchronize(guard.e1), "event sync");
       float ms = 0.0f;
-      hip_check(hipEventElapsedTime(&ms, e0, e1), "event elapsed");
+      hip_check(hipEventElapsedTime(&ms, guard.e0, guard.e1), "event elapsed");
       const double per = ms / reps;
       if (ms_out) ms_out[k] = per;
       if (per < best_ms) {
@@ -2311,10 +2445,7 @@ int heom_autotune(heom_model* m, int n_traj, int precision, int reps, int* kerne
         best = k;
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    m->kernel[precision] = best;
-    m->timing = saved_timing;
+    guard.kernel = best;
     if (kernel_out) *kernel_out = best;
   });
 }

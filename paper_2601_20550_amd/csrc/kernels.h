@@ -45,6 +45,42 @@ bool mfma_supported(int d, int n_modes, const int* dims);
 template <typename T>
 void launch_rhs_mfma(const DevOps<T>& op, const T* Hp, const T* in, const T* y, T* out, double coef,
                      int n_traj, int variant, hipStream_t stream);
+// True when launch_rhs_mfma has a compile-time mode shape for this model
+// (otherwise variants 0 and 1 run the same kernel).
+template <typename T>
+bool mfma_static_shape(const DevOps<T>& op);
+
+// Compute units of the current device (cached).
+int cu_count();
+
+// Arguments of the matrix-core kernel for three-mode models in the (S; 4, 4)
+// device basis a = 16 a_S + 4 a_M + a_F (FP32): H in that basis, the tables of
+// DevOps, the table index of the modes in the roles S, M, F and their
+// single-mode operators (row-major; vS is NB x NB with NB = d / 16).
+struct KronArgs {
+  const float* H;
+  const float* gamma;
+  const float* gamma_im;
+  const int* nb_ptr;
+  const int* nb_idx;
+  const float* nb_a;
+  int n_modes;
+  int n_ado;
+  int mode_S, mode_M, mode_F;
+  float vS[64];
+  float vM[16];
+  float vF[16];
+};
+
+// Roles (S, M, F) of the modes when the model has the (S; 4, 4) structure
+// the kernel needs (three modes, d = 64 or 80, two modes of 4 levels and the
+// slow one of d / 16 levels); false otherwise.
+bool kron_roles(int d, int n_modes, const int* dims, int* roles);
+bool kron_supported(int d, int n_modes, const int* dims);
+// out = y + coef L(in) (or L(in) when y is null) over n_traj trajectories in
+// the device basis; one wave per real plane of an output matrix.
+void launch_rhs_kron(const KronArgs& a, int d, const float* in, const float* y, float* out, double coef, int n_traj,
+                     hipStream_t stream);
 
 // One model instance inside a multi-instance launch (see
 // launch_rhs_mfma_multi): its tables, its padded H, the input, base (y, may be

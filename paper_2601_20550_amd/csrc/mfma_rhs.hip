@@ -32,6 +32,18 @@
 
 namespace heom {
 
+int cu_count() {
+  static int count = 0;
+  if (count == 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      count = prop.multiProcessorCount;
+    if (count <= 0) count = 256;
+  }
+  return count;
+}
+
 namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -68,15 +80,15 @@ struct StaticShape {
   __device__ StaticShape(const int*, const int*, int, int) {}
   __device__ static constexpr int nm() { return NM; }
   __device__ static constexpr int dim(int s) { return s == 0 ? D0 : s == 1 ? D1 : s == 2 ? D2 : D3; }
-  __device__ static constexpr int stride(int s) {
+  __host__ __device__ static constexpr int stride(int s) {
     return s == 0 ? D1 * D2 * D3 : s == 1 ? D2 * D3 : s == 2 ? D3 : 1;
   }
   __device__ static constexpr int d() { return D0 * D1 * D2 * D3; }
-  static bool matches(int nm_, const int* dims) {
+  static bool matches(int nm_, const int* dims, const int* strides) {
     if (nm_ != NM) return false;
     const int D[4] = {D0, D1, D2, D3};
     for (int s = 0; s < NM; ++s)
-      if (dims[s] != D[s]) return false;
+      if (dims[s] != D[s] || strides[s] != stride(s)) return false;
     return true;
   }
 };
@@ -699,19 +711,6 @@ __global__ __launch_bounds__((NB * 64 * wpr_of<T, NB>()), MINW) void rhs_mfma_mu
   }
 }
 
-int g_cu_count = 0;
-
-int cu_count() {
-  if (g_cu_count == 0) {
-    int dev = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-      g_cu_count = prop.multiProcessorCount;
-    if (g_cu_count <= 0) g_cu_count = 256;
-  }
-  return g_cu_count;
-}
-
 template <typename T, int NB, typename Shape, int VW>
 void launch_shape_vw(const DevOps<T>& op, const T* Hp, const T* in, const T* y, T* out, T coef, long long n_items,
                      int wg_per_cu, hipStream_t stream) {
@@ -770,6 +769,12 @@ bool mfma_supported(int d, int n_modes, const int* dims) {
 }
 
 template <typename T>
+bool mfma_static_shape(const DevOps<T>& op) {
+  return (sizeof(T) == 8 && StaticShape<3, 4, 4, 5>::matches(op.n_modes, op.dims, op.strides)) ||
+         StaticShape<1, 6>::matches(op.n_modes, op.dims, op.strides);
+}
+
+template <typename T>
 void launch_rhs_mfma(const DevOps<T>& op, const T* Hp, const T* in, const T* y, T* out, double coef, int n_traj,
                      int variant, hipStream_t stream) {
   const long long n_items = static_cast<long long>(n_traj) * op.n_ado;
@@ -787,9 +792,9 @@ void launch_rhs_mfma(const DevOps<T>& op, const T* Hp, const T* in, const T* y, 
   // registers live and won for (4,4,5) in FP32 (101.0 vs 103.8 ms per launch
   // at 128 trajectories) and for (5,5) in both precisions (FP32 15.0 vs
   // 22.7 ms at 2048 trajectories, FP64 7.5 vs 12.6 ms at 512).
-  if (specialised && sizeof(T) == 8 && StaticShape<3, 4, 4, 5>::matches(op.n_modes, op.dims)) {
+  if (specialised && sizeof(T) == 8 && StaticShape<3, 4, 4, 5>::matches(op.n_modes, op.dims, op.strides)) {
     launch_shape<T, 5, StaticShape<3, 4, 4, 5>>(op, Hp, in, y, out, c, n_items, wg, stream);
-  } else if (specialised && StaticShape<1, 6>::matches(op.n_modes, op.dims)) {
+  } else if (specialised && StaticShape<1, 6>::matches(op.n_modes, op.dims, op.strides)) {
     launch_shape<T, 1, StaticShape<1, 6>>(op, Hp, in, y, out, c, n_items, wg, stream);
   } else {
     switch ((op.d + 15) / 16) {
@@ -868,6 +873,8 @@ void launch_rhs_mfma_multi(const InstDesc<T>* desc, int n_inst, int nb, int vw, 
 template void launch_rhs_mfma_multi<float>(const InstDesc<float>*, int, int, int, double, long long, hipStream_t);
 template void launch_rhs_mfma_multi<double>(const InstDesc<double>*, int, int, int, double, long long, hipStream_t);
 
+template bool mfma_static_shape<float>(const DevOps<float>&);
+template bool mfma_static_shape<double>(const DevOps<double>&);
 template bool mfma_supported<float>(int, int, const int*);
 template bool mfma_supported<double>(int, int, const int*);
 template void launch_rhs_mfma<float>(const DevOps<float>&, const float*, const float*, const float*, float*,

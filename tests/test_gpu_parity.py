@@ -52,7 +52,12 @@ def _relerr(a, b):
 CASES = [("cfg1", None), ("cfg2", None), ("cfg2", 2), ("cfg3", 2), ("paper_scale", 2)]
 
 
-KERNELS = ["generic", "mfma", "mfma_dyn"]
+KERNELS = ["generic", "mfma", "mfma_dyn", "kron"]
+
+
+def _kron_applies(which, prec):
+    # the (S; 4, 4) matrix-core kernel: FP32, three modes of (4|5, 4, 4) levels
+    return prec == "fp32" and which in ("cfg3", "paper_scale")
 
 
 @pytest.mark.parametrize("which,depth", CASES)
@@ -63,6 +68,11 @@ def test_rhs_parity(which, depth, adjoint, prec, kernel):
     params = _params(which, depth)
     o = om.build(params)
     m = P.heom_model_build(params)
+    if kernel == "kron" and not _kron_applies(which, prec):
+        with pytest.raises(P.heom2dvs.HeomError) as e:
+            P.heom_model_set_kernel(m, prec, kernel)
+        assert e.value.code == P.heom2dvs.HEOM_ERR_PARAM
+        return
     P.heom_model_set_kernel(m, prec, kernel)
     x = w.random_hierarchy(3, len(o.hier), o.d, seed=11, scale_by_depth=_depth_scale(o))
     xin = P.State(m, 3, prec)
@@ -108,6 +118,8 @@ def test_rhs_parity_full_depth_three_modes():
     ref = oh.rhs(o, x)
     for kernel in KERNELS:
         for prec, tol in (("fp64", 1e-12), ("fp32", 2e-6)):
+            if kernel == "kron" and prec == "fp64":
+                continue
             P.heom_model_set_kernel(m, prec, kernel)
             a, b = P.State(m, 2, prec), P.State(m, 2, prec)
             a.upload(x)
@@ -118,7 +130,9 @@ def test_rhs_parity_full_depth_three_modes():
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_rk4_steps_parity(prec, tol, kernel):
-    params = _params("cfg2", 3)
+    params = _params("cfg3", 2) if kernel == "kron" else _params("cfg2", 3)
+    if kernel == "kron" and prec == "fp64":
+        pytest.skip("the (S; 4, 4) kernel is FP32 only")
     o = om.build(params)
     m = P.heom_model_build(params)
     P.heom_model_set_kernel(m, prec, kernel)
@@ -146,7 +160,7 @@ def full_size_refs():
     return params, x, oh.rk4_step(o, x), oh.rk4_step(o, g)
 
 
-@pytest.mark.parametrize("kernel", ["mfma", "mfma_dyn"])
+@pytest.mark.parametrize("kernel", ["mfma", "mfma_dyn", "kron"])
 def test_full_size_batched_step_sampled(full_size_refs, kernel):
     """Three-mode depth-6 model, 128 trajectories (the benchmark batch) with
     either matrix-core instantiation the benchmark's autotuner may choose:
@@ -567,6 +581,8 @@ def test_rhs_parity_rate_filtered_hierarchy(which, depth, cut, prec, kernel):
     assert len(o.hier) < len(om.build(_params(which, depth)).hier)
     m = P.heom_model_build(params)
     assert m.n_ado == len(o.hier)
+    if kernel == "kron" and not _kron_applies(which, prec):
+        pytest.skip("the (S; 4, 4) kernel needs FP32 and the three-mode shape")
     P.heom_model_set_kernel(m, prec, kernel)
     x = w.random_hierarchy(2, len(o.hier), o.d, seed=21, scale_by_depth=_depth_scale(o))
     xin = P.State(m, 2, prec)
@@ -668,3 +684,45 @@ def test_rhs_parity_padded_multiple_of_four(keep, prec, kernel):
     tol = 1e-12 if prec == "fp64" else 2e-6
     assert _relerr(xout.download_range(0, 1)[0], ref[0]) < tol
     assert _relerr(xout.download_range(B - 1, 1)[0], ref[1]) < tol
+
+
+@pytest.mark.parametrize("which", ["cfg3", "paper_scale"])
+def test_device_basis_roundtrip_and_default_kernel(which):
+    # three-mode (S; 4, 4) models keep their matrices in the reordered device
+    # basis: upload / download must give back the caller's arrays exactly, and
+    # the FP32 default is the (S; 4, 4) kernel
+    params = _params(which, 1)
+    o = om.build(params)
+    m = P.heom_model_build(params)
+    assert P.heom_model_get_kernel(m, "fp32") == "kron"
+    x = w.random_hierarchy(3, len(o.hier), o.d, seed=2)
+    s = P.State(m, 3, "fp64")
+    s.upload(x)
+    assert np.array_equal(s.download(), x)
+    s.upload_range(1, x[2:3])
+    assert np.array_equal(s.download_range(1, 1)[0], x[2])
+    ops = m.operators()
+    assert np.array_equal(ops["H"], o.H) or _relerr(ops["H"], o.H) < 1e-13
+
+
+@pytest.mark.parametrize("which,depth,B", [("cfg3", 1, 3000), ("paper_scale", 1, 2000)])
+def test_kron_many_items_per_wave(which, depth, B):
+    # thousands of trajectories: every wave of the persistent grid processes
+    # many (matrix, plane) items; picked trajectories against the oracle and
+    # untouched ones against the ground-state step
+    params = _params(which, depth)
+    o = om.build(params)
+    m = P.heom_model_build(params)
+    P.heom_model_set_kernel(m, "fp32", "kron")
+    s = P.State(m, B, "fp32")
+    s.set_ground()
+    x = w.random_hierarchy(3, len(o.hier), o.d, seed=4, scale_by_depth=_depth_scale(o))
+    picks = [0, B // 2 + 3, B - 1]
+    for i, b in enumerate(picks):
+        s.upload_range(b, x[i:i + 1])
+    P.heom_propagate(m, s, 2)
+    ref = oh.propagate(o, x, 2)
+    for i, b in enumerate(picks):
+        assert _relerr(s.download_range(b, 1)[0], ref[i]) < 1e-5
+    g = oh.propagate(o, oh.ground_state_hierarchy(o), 2)
+    assert _relerr(s.download_range(1, 1)[0], g) < 1e-5
