@@ -413,8 +413,9 @@ int heom_batch_response_2d(heom_batch* batch, const heom_state* const* rho_eq, c
  *                         levels); state upload / download convert from and
  *                         to the caller's basis (mode 0 slowest), so the
  *                         reordering is invisible at this interface.
- * Models start on HEOM_KERNEL_KRON (FP32) where it applies, otherwise on
- * HEOM_KERNEL_MFMA where it fits the LDS (FP32 d <= 112, FP64 d <= 80) and
+ * (measured slower than HEOM_KERNEL_MFMA on MI355X at the three-mode depth-6
+ * benchmark shape, so it is not the default; heom_autotune times it).
+ * Models start on HEOM_KERNEL_MFMA where it fits the LDS (FP32 d <= 112, FP64 d <= 80) and
  * every mode keeps at most 8 levels (the single-mode operators are staged in
  * 8 x 8 LDS slots), and on HEOM_KERNEL_GENERIC otherwise;
  * heom_model_set_kernel refuses a kernel outside these limits

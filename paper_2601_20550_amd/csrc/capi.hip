@@ -276,7 +276,21 @@ void upload_model(heom_model* m) {
   m->quanta_dev.resize(hm.d);
   for (int a = 0; a < hm.d; ++a) m->quanta_dev[a] = hm.quanta[m->perm.empty() ? a : m->perm[a]];
   m->H64 = upload_vec(Hd, st);
-  m->H32 = f32(Hd);
+  // FP32 copy of H shifted by (min + max of its diagonal) / 2 times the
+  // identity: the commutator [H, rho] is unchanged, while the products H rho
+  // and rho H whose difference it is shrink (about half the spectral range),
+  // and with them their FP32 rounding
+  std::vector<double> Hs = Hd;
+  {
+    double lo = Hd[0], hi = Hd[0];
+    for (int a = 0; a < hm.d; ++a) {
+      lo = std::min(lo, Hd[static_cast<size_t>(a) * hm.d + a]);
+      hi = std::max(hi, Hd[static_cast<size_t>(a) * hm.d + a]);
+    }
+    const double c = 0.5 * (lo + hi);
+    for (int a = 0; a < hm.d; ++a) Hs[static_cast<size_t>(a) * hm.d + a] -= c;
+  }
+  m->H32 = f32(Hs);
   std::vector<double> vpack;
   int v_off[4] = {0, 0, 0, 0};
   for (int s = 0; s < hm.n_modes; ++s) {
@@ -335,6 +349,8 @@ void upload_model(heom_model* m) {
     for (int a = 0; a < d; ++a)
       for (int c = 0; c < d; ++c) hp[static_cast<size_t>(a) * DP + c] = Hd[static_cast<size_t>(a) * d + c];
     m->Hp64 = upload_vec(hp, st);
+    for (int a = 0; a < d; ++a)
+      for (int c = 0; c < d; ++c) hp[static_cast<size_t>(a) * DP + c] = Hs[static_cast<size_t>(a) * d + c];
     m->Hp32 = f32(hp);
     if (!heom::mfma_supported<double>(d, hm.n_modes, hm.dims)) m->kernel[HEOM_FP64] = HEOM_KERNEL_GENERIC;
     if (!heom::mfma_supported<float>(d, hm.n_modes, hm.dims)) m->kernel[HEOM_FP32] = HEOM_KERNEL_GENERIC;
@@ -383,7 +399,6 @@ void upload_model(heom_model* m) {
         k.vF[e] = static_cast<float>(hm.v[roles[2]][e]);
       }
     }
-    m->kernel[HEOM_FP32] = HEOM_KERNEL_KRON;
   }
   m->red_result = DevBuf(sizeof(double) * 4);
   m->has_device = true;
@@ -2348,8 +2363,7 @@ int heom_model_set_kernel(heom_model* m, int precision, int kernel) {
     if (kernel < HEOM_KERNEL_AUTO || kernel > HEOM_KERNEL_KRON) throw HeomError(HEOM_ERR_PARAM, "bad kernel");
     const bool ok = precision == HEOM_FP64 ? heom::mfma_supported<double>(m->hm.d, m->hm.n_modes, m->hm.dims)
                                            : heom::mfma_supported<float>(m->hm.d, m->hm.n_modes, m->hm.dims);
-    if (kernel == HEOM_KERNEL_AUTO)
-      kernel = (precision == HEOM_FP32 && m->kron) ? HEOM_KERNEL_KRON : ok ? HEOM_KERNEL_MFMA : HEOM_KERNEL_GENERIC;
+    if (kernel == HEOM_KERNEL_AUTO) kernel = ok ? HEOM_KERNEL_MFMA : HEOM_KERNEL_GENERIC;
     if (kernel == HEOM_KERNEL_KRON && (precision != HEOM_FP32 || !m->kron))
       throw HeomError(HEOM_ERR_PARAM, "the (S;4,4) matrix-core kernel needs FP32 and three modes of (4|5, 4, 4) levels");
     if ((kernel == HEOM_KERNEL_MFMA || kernel == HEOM_KERNEL_MFMA_DYN) && !ok)

@@ -315,12 +315,19 @@ def test_response_2d_generic_kernel():
 
 
 def test_autotune_picks_a_measured_kernel():
-    params = _params("cfg2", 3)
-    m = P.heom_model_build(params)
-    best, ms = P.heom_autotune(m, 4, "fp32", reps=1)
-    assert set(ms) == {"generic", "mfma", "mfma_dyn"}
-    assert best == min(ms, key=ms.get)
-    assert P.heom_model_get_kernel(m, "fp32") == best
+    # (5, 5) levels: no compile-time shape, so "mfma_dyn" would run the same
+    # code as "mfma" and is not timed; the single mode of 6 levels has one
+    # (both are timed); the three-mode (4, 4, 5) model adds the (S; 4, 4)
+    # kernel in FP32
+    for which, depth, prec, want in (("cfg2", 3, "fp32", {"generic", "mfma"}),
+                                     ("cfg1", None, "fp64", {"generic", "mfma", "mfma_dyn"}),
+                                     ("cfg3", 1, "fp32", {"generic", "mfma", "kron"})):
+        m = P.heom_model_build(_params(which, depth))
+        P.heom_model_set_kernel(m, prec, "generic")
+        best, ms = P.heom_autotune(m, 4, prec, reps=2)
+        assert set(ms) == want, which
+        assert best == min(ms, key=ms.get)
+        assert P.heom_model_get_kernel(m, prec) == best
 
 
 def test_response_2d_batching_and_methods_agree():
@@ -689,12 +696,11 @@ def test_rhs_parity_padded_multiple_of_four(keep, prec, kernel):
 @pytest.mark.parametrize("which", ["cfg3", "paper_scale"])
 def test_device_basis_roundtrip_and_default_kernel(which):
     # three-mode (S; 4, 4) models keep their matrices in the reordered device
-    # basis: upload / download must give back the caller's arrays exactly, and
-    # the FP32 default is the (S; 4, 4) kernel
+    # basis: upload / download must give back the caller's arrays exactly
     params = _params(which, 1)
     o = om.build(params)
     m = P.heom_model_build(params)
-    assert P.heom_model_get_kernel(m, "fp32") == "kron"
+    assert P.heom_model_get_kernel(m, "fp32") == "mfma"
     x = w.random_hierarchy(3, len(o.hier), o.d, seed=2)
     s = P.State(m, 3, "fp64")
     s.upload(x)
