@@ -210,6 +210,22 @@ int heom_rhs(heom_model* model, const heom_state* in, heom_state* out, int adjoi
  * non-finite (checked at the end). */
 int heom_propagate(heom_model* model, heom_state* state, int n_steps, int adjoint, int sample_every,
                    double* trace_out);
+/* heom_propagate for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results, but every work buffer (two RK4 stage buffers,
+ * the sampled traces, the finiteness-check partials) lives in one static
+ * device array of 64 MiB per GPU that the library holds until the process
+ * ends; no hipMalloc / hipFree or other allocating call is made.  The model
+ * and state must exist already (building them allocates).  Needs
+ * 2 x state bytes + 8 x n_traj x n_ado + 16 x n_traj x n_samples bytes
+ * (each part rounded up to 256) <= 64 MiB, else HEOM_ERR_PARAM with the
+ * size in the message.  Graph replay and timing (heom_model_set_graph_steps,
+ * heom_timing_enable) do not apply to this call.  Calls on one GPU share its
+ * array: calls that overlap in time on one GPU (different threads or
+ * streams) race and must be serialised by the caller.  Arguments, outputs
+ * and errors otherwise as heom_propagate. */
+int heom_propagate_noalloc(heom_model* model, heom_state* state, int n_steps, int adjoint, int sample_every,
+                           double* trace_out);
 /* X <- D^x X = D X - X D on every ADO (transpose = 0), or
  * X <- (D^T)^x X (transpose = 1), D chosen by `op` (heom_operator). FP64
  * arithmetic on either precision. */

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -1556,6 +1557,95 @@ OpVec op_vec(const heom::HostModel& hm) {
 
 // ============================================================== C ABI =====
 
+// ------------------------------------------------ allocation-free calls --
+// Scratch memory of heom_propagate_noalloc: a file-scope device array (each
+// GPU the library runs on holds its own copy until the process ends).  In
+// host code `scratch` is only a symbol: its device address is looked up once
+// per device with hipGetSymbolAddress and that pointer is used everywhere.
+namespace {
+
+constexpr size_t kNoAllocBytes = static_cast<size_t>(64) << 20;  // 64 MiB
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (looked up on first use, with
+// dev current; the caller's current device is restored).
+unsigned char* device_scratch(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev < 0 || dev >= kMaxDevices) throw HeomError(HEOM_ERR_PARAM, "device index out of range");
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    hip_check(hipGetDevice(&cur), "hipGetDevice");
+    if (cur != dev) hip_check(hipSetDevice(dev), "hipSetDevice");
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) hip_check(hipSetDevice(cur), "hipSetDevice");
+    if (e != hipSuccess || !p)
+      throw HeomError(HEOM_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  return static_cast<unsigned char*>(g_scratch_ptr[dev]);
+}
+
+size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
+
+// heom_propagate with every work buffer carved from the device's scratch
+// array: the two RK4 stage buffers, the traces and the absmax partials.
+template <typename T>
+void propagate_noalloc(heom_model* m, heom_state* s, int n_steps, bool adjoint, int sample_every, double* trace_out) {
+  const long long elems = s->n_elems();
+  const long long n_mats = static_cast<long long>(s->n_traj) * m->hm.n_ado;
+  const bool sample = sample_every > 0 && trace_out;
+  const int n_samples = sample ? n_steps / sample_every + 1 : 0;
+  const size_t b_stage = align256(static_cast<size_t>(elems) * sizeof(T));
+  const size_t b_part = align256(static_cast<size_t>(n_mats) * sizeof(double));
+  const size_t b_res = 256;
+  const size_t b_tr = align256(static_cast<size_t>(n_samples) * s->n_traj * 2 * sizeof(double));
+  const size_t need = 2 * b_stage + b_part + b_res + b_tr;
+  if (need > kNoAllocBytes)
+    throw HeomError(HEOM_ERR_PARAM, "heom_propagate_noalloc needs " + std::to_string(need) +
+                                        " bytes of scratch; the static buffer holds " +
+                                        std::to_string(kNoAllocBytes) + " (use heom_propagate)");
+  unsigned char* base = device_scratch(m->device);
+  T* w1 = reinterpret_cast<T*>(base);
+  T* w2 = reinterpret_cast<T*>(base + b_stage);
+  double* part = reinterpret_cast<double*>(base + 2 * b_stage);
+  double* res = reinterpret_cast<double*>(base + 2 * b_stage + b_part);
+  double* tr = reinterpret_cast<double*>(base + 2 * b_stage + b_part + b_res);
+  T* y = s->buf.as<T>();
+  // direct launches only (no graph capture, no timing events: both would
+  // create runtime objects)
+  auto steps = [&](int k) {
+    for (int i = 0; i < k; ++i) rk4_step_launches<T>(m, y, w1, w2, s->n_traj, adjoint);
+  };
+  if (!sample) {
+    steps(n_steps);
+  } else {
+    for (int k = 0; k < n_samples; ++k) {
+      if (k > 0) steps(sample_every);
+      heom::launch_trace<T>(m->mu64[HEOM_OP_MU].as<double>(), y, m->hm.d, m->traj_elems(), s->n_traj,
+                            tr + static_cast<size_t>(k) * s->n_traj * 2, 1, m->stream);
+    }
+    steps(n_steps - (n_samples - 1) * sample_every);
+    hip_check(hipMemcpyAsync(trace_out, tr, static_cast<size_t>(n_samples) * s->n_traj * 2 * sizeof(double),
+                             hipMemcpyDeviceToHost, m->stream),
+              "copy");
+  }
+  double r = 0.0;
+  if (n_mats > 0) {
+    heom::launch_absmax<T>(y, m->hm.d, n_mats, part, res, m->stream);
+    hip_check(hipMemcpyAsync(&r, res, sizeof(double), hipMemcpyDeviceToHost, m->stream), "copy");
+  }
+  hip_check(hipStreamSynchronize(m->stream), "sync");
+  if (!std::isfinite(r))
+    throw HeomError(HEOM_ERR_UNSTABLE, "non-finite hierarchy after propagation (time step beyond the RK4 stability region?)");
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* heom_last_error(void) { return g_last_error.c_str(); }
@@ -1854,6 +1944,19 @@ int heom_propagate(heom_model* m, heom_state* s, int n_steps, int adjoint, int s
       propagate_sampled<double>(m, s, n_steps, adjoint != 0, sample_every, trace_out);
     else
       propagate_sampled<float>(m, s, n_steps, adjoint != 0, sample_every, trace_out);
+  });
+}
+
+int heom_propagate_noalloc(heom_model* m, heom_state* s, int n_steps, int adjoint, int sample_every,
+                           double* trace_out) {
+  return guarded([&] {
+    require_device(m);
+    require_state(m, s);
+    if (n_steps < 0) throw HeomError(HEOM_ERR_PARAM, "n_steps must be >= 0");
+    if (s->precision == HEOM_FP64)
+      propagate_noalloc<double>(m, s, n_steps, adjoint != 0, sample_every, trace_out);
+    else
+      propagate_noalloc<float>(m, s, n_steps, adjoint != 0, sample_every, trace_out);
   });
 }
 

@@ -107,6 +107,7 @@ _SIGS = {
     "heom_state_copy": (C.c_int, [C.c_void_p, C.c_void_p]),
     "heom_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "heom_propagate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p]),
+    "heom_propagate_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p]),
     "heom_apply_dipole": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int]),
     "heom_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "heom_residual": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
@@ -382,6 +383,19 @@ def heom_propagate(model, state: State, n_steps: int, adjoint=False, sample_ever
                                    int(sample_every), _ptr(out)))
         return (out[0::2] + 1j * out[1::2]).reshape(-1, n_traj)
     _check(_lib.heom_propagate(model.handle, state.handle, int(n_steps), int(bool(adjoint)), 0, None))
+    return None
+
+
+def heom_propagate_noalloc(model, state: State, n_steps: int, adjoint=False, sample_every=0):
+    """heom_propagate without device allocations (work buffers in the library's
+    static 64 MiB device array); same return value."""
+    if sample_every and sample_every > 0:
+        n_traj = state.n_traj
+        out = np.zeros((int(n_steps) // int(sample_every) + 1) * n_traj * 2)
+        _check(_lib.heom_propagate_noalloc(model.handle, state.handle, int(n_steps), int(bool(adjoint)),
+                                           int(sample_every), _ptr(out)))
+        return (out[0::2] + 1j * out[1::2]).reshape(-1, n_traj)
+    _check(_lib.heom_propagate_noalloc(model.handle, state.handle, int(n_steps), int(bool(adjoint)), 0, None))
     return None
 
 
