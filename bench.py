@@ -34,11 +34,11 @@ sys.path.insert(0, ROOT)
 # scaled by the counters' readings for kernels of known size.  Keyed by the
 # kernel source hash: a changed kernel reports traffic null until re-profiled.
 PROFILED_TRAFFIC = {  # source hash -> kernel choice -> bytes per launch
-    # 4be3b71abfab6a84 differs from the profiled fafb39b13146668d by a comment only
-    # (identical device code apart from the compilation-unit id symbol)
-    "4be3b71abfab6a84": {  # FP32 at this shape: both choices run the runtime-shape kernel
-        "mfma": {"read_GB": 319.7, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
-        "mfma_dyn": {"read_GB": 319.7, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
+    "1e73106a80d7a912": {  # FP32 at this shape: both choices run the runtime-shape kernel
+        "mfma": {"read_GB": 319.4, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
+        "mfma_dyn": {"read_GB": 319.4, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
+        # the FP64 leg: 32 trajectories
+        "fp64:mfma": {"read_GB": 155.6, "write_GB": 16.4, "batch": 32, "precision": "fp64"},
     },
 }
 
@@ -201,11 +201,16 @@ def fp64_leg(P, torch, m, steps, flops_per_traj):
     del s
     avg = k_ms / 1e3 / max(n_launch, 1)
     achieved = flops_per_traj * B / avg / 1e12
-    return {"value": B * m.n_ado * steps / wall, "unit": "ADO-updates/s", "trajectories": B, "steps": steps,
-            "ms_per_step": wall / steps * 1e3, "kernel_choice": prev,
-            "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s",
-                         "frac": achieved / PEAKS["fp64_tflops"], "avg_launch_ms": avg * 1e3,
-                         "launches": n_launch}}
+    out = {"value": B * m.n_ado * steps / wall, "unit": "ADO-updates/s", "trajectories": B, "steps": steps,
+           "ms_per_step": wall / steps * 1e3, "kernel_choice": prev,
+           "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s",
+                        "frac": achieved / PEAKS["fp64_tflops"], "traffic": None, "avg_launch_ms": avg * 1e3,
+                        "launches": n_launch}}
+    prof = PROFILED_TRAFFIC.get(kernel_source_hash(prev), {}).get("fp64:" + prev) if prev in KERNEL_FILES else None
+    if prof and prof["batch"] == B and m.n_ado == 5005 and m.d == 80:
+        out["roofline"]["traffic"] = (prof["read_GB"] + prof["write_GB"]) * 1e9
+        out["roofline"]["traffic_unit"] = "bytes per launch (HBM, calibrated rocprofv3 counters)"
+    return out
 
 
 def spectrum_legs(P, torch, w, m, params, grid, args):
