@@ -390,7 +390,8 @@ int heom_params_vjp(const heom_params* params, const heom_params* dirs, int n_di
 /* A batch of models (instances) of possibly different sizes, propagated
  * together: every RK4 stage is one persistent matrix-core launch per size
  * class ceil(d/16), covering the matrices of all instances of that class
- * (workgroups re-stage H and v_s when they move to another instance).  The
+ * (workgroups re-stage H and v_s when they move to another instance), or one
+ * launch over all classes (heom_batch_set_launch below).  The
  * models are borrowed and must outlive the batch; they must share the device,
  * the stream and the time step, and each needs d <= 112 (FP32) or d <= 80
  * (FP64).  HEOM_ERR_PARAM otherwise. */
@@ -406,6 +407,40 @@ int heom_batch_propagate(heom_batch* batch, heom_state* const* states, int n_ste
  * [n_t2][2][n1][n3] complex for instance i. */
 int heom_batch_response_2d(heom_batch* batch, const heom_state* const* rho_eq, const heom_grid* grid,
                            int precision, double* const* R_out);
+/* Launch form of a batch's RK4 stages:
+ *   HEOM_BATCH_PER_CLASS: one persistent launch per size class and stage.
+ *   HEOM_BATCH_SINGLE   : one persistent launch per stage over every class:
+ *                         its workgroups are split among the classes in
+ *                         proportion to each class's work (matrices x cost
+ *                         per matrix, measured by heom_batch_autotune, else
+ *                         a cost model growing as nb^2 (nb + 1)); a
+ *                         workgroup runs the item code of its class.  Needs
+ *                         every d <= 80 (HEOM_ERR_PARAM otherwise).
+ *   HEOM_BATCH_AUTO     : the form heom_batch_autotune chose, per class
+ *                         before any tuning (the default).
+ * Both forms compute the same stages (results equal to rounding order). */
+typedef enum {
+  HEOM_BATCH_AUTO = 0,
+  HEOM_BATCH_PER_CLASS = 1,
+  HEOM_BATCH_SINGLE = 2
+} heom_batch_launch;
+int heom_batch_set_launch(heom_batch* batch, int launch);
+/* The form HEOM_BATCH_AUTO resolves to now (or the one set). */
+int heom_batch_get_launch(const heom_batch* batch, int* launch_out);
+/* Replay every `steps` RK4 steps of a batched propagation as one captured HIP
+ * graph (0: direct launches, the default).  A graph is captured per
+ * propagation call on a private stream and replayed on the batch's stream;
+ * if capture fails the batch falls back to direct launches. */
+int heom_batch_set_graph_steps(heom_batch* batch, int steps);
+/* Measure the launch forms on scratch states of n_traj trajectories per
+ * instance (ground state, precision HEOM_FP32 or HEOM_FP64): the time per
+ * matrix of each size class alone (kept as the single launch's work
+ * weights), then `reps` RK4 steps per class launches and, where allowed,
+ * as single launches; HEOM_BATCH_AUTO then resolves to the faster.
+ * ms_out (may be null): [per-class, single] milliseconds per RK4 step (NaN
+ * when the single form is not allowed).  Allocates 3 x n_traj hierarchies per
+ * instance for the duration of the call. */
+int heom_batch_autotune(heom_batch* batch, int precision, int n_traj, int reps, double* ms_out);
 
 /* ------------------------------------------------------ kernel choice -- */
 /* Implementations of the fused RHS / RK4-stage kernel:

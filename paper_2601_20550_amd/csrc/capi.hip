@@ -879,12 +879,31 @@ struct heom_batch {
   std::vector<heom_model*> models;
   hipStream_t stream = nullptr;
   double dt = 0.0;
+  int launch = HEOM_BATCH_AUTO;   // requested launch form
+  int tuned = 0;                  // form chosen by heom_batch_autotune (0: none yet)
+  double class_cost[8] = {};      // measured time per matrix of each size class (0: cost model)
+  int graph_steps = 0;            // RK4 steps per captured graph (0: direct launches)
+  hipStream_t cap_stream = nullptr;
+  ~heom_batch() {
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+  int resolved_launch() const {
+    if (launch != HEOM_BATCH_AUTO) return launch;
+    return tuned ? tuned : HEOM_BATCH_PER_CLASS;
+  }
 };
 
 namespace {
 
+// Relative cost of one matrix of size class nb when nothing was measured:
+// matrix-core work grows as nb^3, neighbour and staging traffic as nb^2.
+double default_class_cost(int nb) { return static_cast<double>(nb) * nb * (nb + 1); }
+
 // Descriptor sets of one batched propagation: per size class and for both
-// generators, the four stage role assignments of the Horner RK4 step.
+// generators, the four stage role assignments of the Horner RK4 step.  With
+// the single-launch form the classes' descriptors are also concatenated and
+// the launch's workgroups split among the classes in proportion to their
+// estimated work (items x cost per item).
 template <typename T>
 struct BatchProp {
   struct Class {
@@ -894,8 +913,27 @@ struct BatchProp {
   };
   std::vector<Class> classes;
   std::vector<DevBuf> w1, w2;
+  bool single = false;
+  DevBuf fdesc[2][4], fcls;
+  int n_cls = 0, waves = 0, grid = 0;
+  size_t lds = 0;
+  std::vector<heom::FusedClass> fhost;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int gsteps[2] = {0, 0};
+
+  BatchProp() = default;
+  BatchProp(const BatchProp&) = delete;
+  BatchProp& operator=(const BatchProp&) = delete;
+  ~BatchProp() {
+    for (auto& e : gexec)
+      if (e) (void)hipGraphExecDestroy(e);
+  }
 
   void build(heom_batch* b, const std::vector<T*>& ys, const std::vector<int>& n_traj) {
+    build_as(b, ys, n_traj, b->resolved_launch());
+  }
+
+  void build_as(heom_batch* b, const std::vector<T*>& ys, const std::vector<int>& n_traj, int form) {
     const int n = static_cast<int>(b->models.size());
     std::map<int, std::vector<int>> by_nb;
     for (int i = 0; i < n; ++i) by_nb[(b->models[i]->hm.d + 15) / 16].push_back(i);
@@ -909,6 +947,8 @@ struct BatchProp {
       w2[i] = DevBuf(bytes);
     }
     classes.clear();
+    std::vector<heom::InstDesc<T>> all[2][4];
+    std::vector<int> nbs;
     for (auto& kv : by_nb) {
       Class c;
       c.nb = kv.first;
@@ -939,22 +979,185 @@ struct BatchProp {
             h.push_back(d);
           }
           c.n_items = begin;
+          all[a][st].insert(all[a][st].end(), h.begin(), h.end());
           c.desc[a][st] = upload_vec(h, b->stream);
         }
+      nbs.push_back(c.nb);
       classes.push_back(std::move(c));
     }
+    single = form == HEOM_BATCH_SINGLE;
+    if (!single) return;
+    waves = heom::fused_block_waves<T>(nbs.data(), static_cast<int>(nbs.size()));
+    if (waves == 0) throw HeomError(HEOM_ERR_PARAM, "single-launch batches need every d <= 80");
+    lds = 0;
+    for (int nb : nbs) lds = std::max(lds, heom::fused_lds_bytes<T>(nb));
+    const long long G = static_cast<long long>(heom::cu_count()) * heom::fused_workgroups_per_cu<T>(waves, lds);
+    double total = 0.0;
+    std::vector<double> w(classes.size());
+    for (size_t c = 0; c < classes.size(); ++c) {
+      const double cost = b->class_cost[classes[c].nb] > 0.0 ? b->class_cost[classes[c].nb]
+                                                              : default_class_cost(classes[c].nb);
+      w[c] = cost * static_cast<double>(classes[c].n_items);
+      total += w[c];
+    }
+    fhost.clear();
+    int begin = 0, inst = 0;
+    for (size_t c = 0; c < classes.size(); ++c) {
+      long long wg = total > 0.0 ? std::llround(static_cast<double>(G) * w[c] / total) : 1;
+      wg = std::max<long long>(1, std::min<long long>(wg, std::max<long long>(1, classes[c].n_items)));
+      heom::FusedClass f;
+      f.nb = classes[c].nb;
+      f.vw = classes[c].vw;
+      f.inst_first = inst;
+      f.n_inst = classes[c].n_inst;
+      f.n_items = classes[c].n_items;
+      f.wg_begin = begin;
+      f.wg_end = begin + static_cast<int>(wg);
+      begin = f.wg_end;
+      inst += classes[c].n_inst;
+      fhost.push_back(f);
+    }
+    grid = begin;
+    n_cls = static_cast<int>(fhost.size());
+    fcls = upload_vec(fhost, b->stream);
+    for (int a = 0; a < 2; ++a)
+      for (int st = 0; st < 4; ++st) fdesc[a][st] = upload_vec(all[a][st], b->stream);
   }
 
-  void steps(heom_batch* b, int n_steps, bool adjoint) {
+  void stage_launch(int st, bool adjoint, double coef, hipStream_t stream) {
+    const int a = adjoint ? 1 : 0;
+    if (single) {
+      heom::launch_rhs_mfma_fused<T>(fcls.as<heom::FusedClass>(), n_cls, fdesc[a][st].template as<heom::InstDesc<T>>(),
+                                     waves, lds, grid, coef, stream);
+      return;
+    }
+    for (auto& c : classes)
+      heom::launch_rhs_mfma_multi<T>(c.desc[a][st].template as<heom::InstDesc<T>>(), c.n_inst, c.nb, c.vw, coef,
+                                     c.n_items, stream);
+  }
+
+  void direct_steps(heom_batch* b, int n_steps, bool adjoint, hipStream_t stream) {
     const double h = b->dt;
     const double coef[4] = {h / 4.0, h / 3.0, h / 2.0, h};
     for (int k = 0; k < n_steps; ++k)
-      for (int st = 0; st < 4; ++st)
-        for (auto& c : classes)
-          heom::launch_rhs_mfma_multi<T>(c.desc[adjoint ? 1 : 0][st].template as<heom::InstDesc<T>>(), c.n_inst,
-                                         c.nb, c.vw, coef[st], c.n_items, b->stream);
+      for (int st = 0; st < 4; ++st) stage_launch(st, adjoint, coef[st], stream);
+  }
+
+  // graph of b->graph_steps RK4 steps (captured on first use; null when
+  // capture fails, which turns graphs off for the batch)
+  hipGraphExec_t graph(heom_batch* b, bool adjoint) {
+    const int a = adjoint ? 1 : 0;
+    if (gexec[a] && gsteps[a] == b->graph_steps) return gexec[a];
+    if (gexec[a]) {
+      (void)hipGraphExecDestroy(gexec[a]);
+      gexec[a] = nullptr;
+    }
+    if (!b->cap_stream) hip_check(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "stream create");
+    hip_check(hipStreamSynchronize(b->stream), "sync");
+    hipGraph_t g = nullptr;
+    bool ok = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+    if (ok) {
+      try {
+        direct_steps(b, b->graph_steps, adjoint, b->cap_stream);
+      } catch (...) {
+        ok = false;
+      }
+      ok = (hipStreamEndCapture(b->cap_stream, &g) == hipSuccess) && ok && g;
+    }
+    if (ok) ok = hipGraphInstantiate(&gexec[a], g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    if (!ok) {
+      gexec[a] = nullptr;
+      b->graph_steps = 0;
+      return nullptr;
+    }
+    gsteps[a] = b->graph_steps;
+    return gexec[a];
+  }
+
+  void steps(heom_batch* b, int n_steps, bool adjoint) {
+    if (b->graph_steps > 0 && n_steps >= b->graph_steps) {
+      hipGraphExec_t ex = graph(b, adjoint);
+      if (ex) {
+        const int reps = n_steps / gsteps[adjoint ? 1 : 0];
+        for (int r = 0; r < reps; ++r) hip_check(hipGraphLaunch(ex, b->stream), "graph launch");
+        n_steps -= reps * gsteps[adjoint ? 1 : 0];
+      }
+    }
+    direct_steps(b, n_steps, adjoint, b->stream);
   }
 };
+
+// heom_batch_autotune: per-class time per matrix, then both launch forms.
+template <typename T>
+void batch_autotune(heom_batch* b, int n_traj, int reps, double* ms_out) {
+  const int n = static_cast<int>(b->models.size());
+  std::vector<DevBuf> st(n);
+  std::vector<T*> ys(n);
+  const std::vector<int> nt(n, n_traj);
+  for (int i = 0; i < n; ++i) {
+    const long long te = b->models[i]->traj_elems();
+    st[i] = DevBuf(static_cast<size_t>(n_traj) * te * sizeof(T));
+    ys[i] = st[i].as<T>();
+    heom::launch_set_ground<T>(ys[i], te, n_traj, static_cast<long long>(n_traj) * te, b->stream);
+  }
+  // no graphs while timing; restores the graph setting and frees the events on every exit
+  struct Guard {
+    heom_batch* b;
+    int graph_steps;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Guard() {
+      b->graph_steps = graph_steps;
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } guard{b, b->graph_steps};
+  b->graph_steps = 0;
+  hip_check(hipEventCreate(&guard.e0), "event");
+  hip_check(hipEventCreate(&guard.e1), "event");
+  auto elapsed = [&] {
+    hip_check(hipEventSynchronize(guard.e1), "event sync");
+    float ms = 0.0f;
+    hip_check(hipEventElapsedTime(&ms, guard.e0, guard.e1), "event time");
+    return static_cast<double>(ms);
+  };
+  const double h = b->dt;
+  const double coef[4] = {h / 4.0, h / 3.0, h / 2.0, h};
+  BatchProp<T> pc;
+  pc.build_as(b, ys, nt, HEOM_BATCH_PER_CLASS);
+  pc.direct_steps(b, 1, false, b->stream);  // code objects, caches
+  std::vector<int> nbs;
+  for (auto& c : pc.classes) {
+    nbs.push_back(c.nb);
+    hip_check(hipEventRecord(guard.e0, b->stream), "event record");
+    for (int k = 0; k < reps; ++k)
+      for (int s4 = 0; s4 < 4; ++s4)
+        heom::launch_rhs_mfma_multi<T>(c.desc[0][s4].template as<heom::InstDesc<T>>(), c.n_inst, c.nb, c.vw,
+                                       coef[s4], c.n_items, b->stream);
+    hip_check(hipEventRecord(guard.e1, b->stream), "event record");
+    b->class_cost[c.nb] = elapsed() / (4.0 * reps * static_cast<double>(std::max<long long>(1, c.n_items)));
+  }
+  hip_check(hipEventRecord(guard.e0, b->stream), "event record");
+  pc.direct_steps(b, reps, false, b->stream);
+  hip_check(hipEventRecord(guard.e1, b->stream), "event record");
+  const double ms_pc = elapsed() / reps;
+  double ms_single = std::nan("");
+  if (heom::fused_block_waves<T>(nbs.data(), static_cast<int>(nbs.size())) > 0) {
+    BatchProp<T> ps;
+    ps.build_as(b, ys, nt, HEOM_BATCH_SINGLE);
+    ps.direct_steps(b, 1, false, b->stream);
+    hip_check(hipEventRecord(guard.e0, b->stream), "event record");
+    ps.direct_steps(b, reps, false, b->stream);
+    hip_check(hipEventRecord(guard.e1, b->stream), "event record");
+    ms_single = elapsed() / reps;
+  }
+  b->tuned = (std::isfinite(ms_single) && ms_single < ms_pc) ? HEOM_BATCH_SINGLE : HEOM_BATCH_PER_CLASS;
+  if (ms_out) {
+    ms_out[0] = ms_pc;
+    ms_out[1] = ms_single;
+  }
+}
 
 template <typename T>
 void batch_response_adjoint(heom_batch* b, const heom_state* const* rho_eq, const heom_grid& g,
@@ -2450,11 +2653,57 @@ int heom_batch_response_2d(heom_batch* b, const heom_state* const* rho_eq, const
       sub.models.assign(b->models.begin() + i0, b->models.begin() + i1);
       sub.stream = b->stream;
       sub.dt = b->dt;
+      sub.launch = b->launch;
+      sub.tuned = b->tuned;
+      std::copy(std::begin(b->class_cost), std::end(b->class_cost), std::begin(sub.class_cost));
+      sub.graph_steps = b->graph_steps;
       if (precision == HEOM_FP64)
         batch_response_adjoint<double>(&sub, rho_eq + i0, g, R_out + i0);
       else
         batch_response_adjoint<float>(&sub, rho_eq + i0, g, R_out + i0);
       i0 = i1;
+    }
+  });
+}
+
+int heom_batch_set_launch(heom_batch* b, int launch) {
+  return guarded([&] {
+    if (!b) throw HeomError(HEOM_ERR_PARAM, "null batch");
+    if (launch < HEOM_BATCH_AUTO || launch > HEOM_BATCH_SINGLE) throw HeomError(HEOM_ERR_PARAM, "bad launch form");
+    if (launch == HEOM_BATCH_SINGLE)
+      for (auto* m : b->models)
+        if ((m->hm.d + 15) / 16 > heom::kFusedMaxNb)
+          throw HeomError(HEOM_ERR_PARAM, "single-launch batches need every d <= 80");
+    b->launch = launch;
+  });
+}
+
+int heom_batch_get_launch(const heom_batch* b, int* out) {
+  return guarded([&] {
+    if (!b || !out) throw HeomError(HEOM_ERR_PARAM, "null argument");
+    *out = b->resolved_launch();
+  });
+}
+
+int heom_batch_set_graph_steps(heom_batch* b, int steps) {
+  return guarded([&] {
+    if (!b || steps < 0) throw HeomError(HEOM_ERR_PARAM, "bad arguments");
+    b->graph_steps = steps;
+  });
+}
+
+int heom_batch_autotune(heom_batch* b, int precision, int n_traj, int reps, double* ms_out) {
+  return guarded([&] {
+    if (!b || n_traj < 1 || reps < 1) throw HeomError(HEOM_ERR_PARAM, "bad arguments");
+    if (precision == HEOM_FP64) {
+      for (auto* m : b->models)
+        if (!heom::mfma_supported<double>(m->hm.d, m->hm.n_modes, m->hm.dims))
+          throw HeomError(HEOM_ERR_PARAM, "FP64 batch needs d <= 80");
+      batch_autotune<double>(b, n_traj, reps, ms_out);
+    } else if (precision == HEOM_FP32) {
+      batch_autotune<float>(b, n_traj, reps, ms_out);
+    } else {
+      throw HeomError(HEOM_ERR_PARAM, "bad precision");
     }
   });
 }

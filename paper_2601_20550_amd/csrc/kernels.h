@@ -104,6 +104,36 @@ template <typename T>
 void launch_rhs_mfma_multi(const InstDesc<T>* desc, int n_inst, int nb, int vw, double coef, long long n_items,
                            hipStream_t stream);
 
+// One size class of a single-launch multi-class stage: its instances are
+// desc[inst_first, inst_first + n_inst) (items numbered from 0 within the
+// class), served by workgroups [wg_begin, wg_end).
+struct FusedClass {
+  int nb;          // ceil(d / 16)
+  int vw;          // vector width (16 / sizeof(T) if every d is divisible by it, else 1)
+  int inst_first;
+  int n_inst;
+  long long n_items;
+  int wg_begin;
+  int wg_end;
+};
+constexpr int kFusedMaxNb = 5;   // classes up to d = 80
+
+// Workgroup width (waves) of the single-launch kernel for these classes, 0 if
+// some class is beyond kFusedMaxNb.
+template <typename T>
+int fused_block_waves(const int* nbs, int n);
+// LDS bytes a class of ceil(d/16) = nb needs (the launch takes the largest).
+template <typename T>
+size_t fused_lds_bytes(int nb);
+// Resident workgroups per CU of the single-launch kernel at this width and LDS.
+template <typename T>
+int fused_workgroups_per_cu(int waves, size_t lds);
+// One RK4 stage (out = y + coef L(in) per instance descriptor) over every
+// class in cls (device array, ordered by wg_begin; the last wg_end = grid).
+template <typename T>
+void launch_rhs_mfma_fused(const FusedClass* cls, int n_cls, const InstDesc<T>* desc, int waves, size_t lds,
+                           int grid, double coef, hipStream_t stream);
+
 // dst = D^x src (or (D^T)^x src) on every ADO, FP64 arithmetic.
 template <typename T>
 void launch_commutator(const double* D, int transpose, const T* src, T* dst, int d,

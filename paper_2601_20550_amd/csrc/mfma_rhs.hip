@@ -25,6 +25,7 @@
 //     constant-folded; DynShape handles any other shape.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <stdexcept>
 #include <string>
 
@@ -210,7 +211,7 @@ __device__ inline void stage_operators(const DevOps<T>& op, const Shape& sh, con
 // [ (w % WPR) JT, ... ) (JT = ceil(NB / WPR)); for the memory phases
 // (neighbour sums, epilogue) it owns the slab of 16 / WPR rows starting at
 // row (16 / WPR) w.
-template <typename T, int NB, typename Shape, int VW, int WPR>
+template <typename T, int NB, typename Shape, int VW, int WPR, bool XL = x_in_lds<T, NB>()>
 __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, const T* __restrict__ in,
                                          const T* y, T* out, T coef, long long item, T* sRe, T* sIm,
                                          const T* sH, const T* sV) {
@@ -368,7 +369,7 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
     const int ds = sh.dim(s), st = sh.stride(s);
     const T* vs = sV + s * 64;
     bool have_w = false;
-    if constexpr (x_in_lds<T, NB>()) {
+    if constexpr (XL) {
       __syncthreads();  // every wave is done with the previous LDS content
       for (int q = p0; q < p1; ++q) {
         const T* rm = in + traj_base + static_cast<long long>(op.nb_idx[q]) * 2 * dd + srow0 * d;
@@ -511,7 +512,7 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
       }
       __syncthreads();
     }
-    if constexpr (x_in_lds<T, NB>()) {
+    if constexpr (XL) {
       // left product: (V_s X_s)[a][c] = sum_k v_s[a_s][k] X_s[a + (k - a_s) st][c];  L += -i V X
       {
         int as[4], r0[4];
@@ -711,6 +712,86 @@ __global__ __launch_bounds__((NB * 64 * wpr_of<T, NB>()), MINW) void rhs_mfma_mu
   }
 }
 
+// ------------------------------------------------ one launch, all classes --
+// Several size classes in one persistent launch.  Workgroups
+// [cls[c].wg_begin, cls[c].wg_end) serve class c; a workgroup has W waves,
+// the widest class's count, and the waves a narrower class does not use end
+// at entry (a workgroup barrier waits only for the waves still running).
+// Each class runs the item code of its own NB, with the neighbour sums X_s in
+// LDS (fewer registers: one register budget serves every class).
+template <typename T>
+__host__ __device__ constexpr int class_waves(int nb) {
+  return nb * ((sizeof(T) == 4 && nb == 5) ? 1 : (nb >= 4 && nb <= 6) ? 2 : 1);
+}
+
+template <typename T, int NB, int VW>
+__device__ __forceinline__ void fused_items(const FusedClass& fc, const InstDesc<T>* __restrict__ desc, T coef,
+                                            unsigned char* smem) {
+  using L = Lds<T, NB>;
+  T* sRe = reinterpret_cast<T*>(smem);
+  T* sIm = sRe + L::PLANE;
+  T* sH = sRe + L::HOFF;
+  T* sV = sRe + L::VOFF;
+  const InstDesc<T>* dc = desc + fc.inst_first;
+  const long long step = fc.wg_end - fc.wg_begin;
+  int cur = -1;
+  for (long long item = static_cast<long long>(blockIdx.x) - fc.wg_begin; item < fc.n_items; item += step) {
+    int lo = 0, hi = fc.n_inst - 1;  // last instance of the class with item_begin <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (dc[mid].item_begin <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const InstDesc<T>& di = dc[lo];
+    const DynShape sh(di.op.dims, di.op.strides, di.op.n_modes, di.op.d);
+    if (lo != cur) {
+      __syncthreads();  // previous instance's LDS reads are complete
+      stage_operators<T, NB, DynShape>(di.op, sh, di.Hp, sRe, sH, sV);
+      cur = lo;
+    }
+    rhs_item<T, NB, DynShape, VW, wpr_of<T, NB>(), true>(di.op, sh, di.in, di.y, di.out, coef,
+                                                        item - di.item_begin, sRe, sIm, sH, sV);
+  }
+}
+
+template <typename T, int W, int NB>
+__device__ __forceinline__ void fused_dispatch(const FusedClass& fc, const InstDesc<T>* desc, T coef,
+                                               unsigned char* smem) {
+  if constexpr (NB <= kFusedMaxNb) {
+    if (fc.nb == NB) {
+      if constexpr (class_waves<T>(NB) <= W) {
+        constexpr int VF = 16 / sizeof(T);
+        if (fc.vw == VF) fused_items<T, NB, VF>(fc, desc, coef, smem);
+        else fused_items<T, NB, 1>(fc, desc, coef, smem);
+      }
+      return;
+    }
+    fused_dispatch<T, W, NB + 1>(fc, desc, coef, smem);
+  }
+}
+
+// at most 128 VGPRs in FP32 (two workgroups of up to 8 waves per CU), 168 in
+// FP64 (one 10-wave workgroup per CU)
+template <typename T>
+constexpr int fused_minw() {
+  return sizeof(T) == 4 ? 4 : 3;
+}
+
+template <typename T, int W>
+__global__ __launch_bounds__(W * 64, fused_minw<T>()) void rhs_mfma_fused_kernel(const FusedClass* __restrict__ cls,
+                                                                                int n_cls,
+                                                                                const InstDesc<T>* __restrict__ desc,
+                                                                                T coef) {
+  extern __shared__ unsigned char smem_raw[];
+  const int b = static_cast<int>(blockIdx.x);
+  int c = 0;
+  while (c + 1 < n_cls && b >= cls[c].wg_end) ++c;
+  const FusedClass fc = cls[c];
+  if (b < fc.wg_begin || b >= fc.wg_end) return;
+  if (static_cast<int>(threadIdx.x >> 6) >= class_waves<T>(fc.nb)) return;
+  fused_dispatch<T, W, 1>(fc, desc, coef, smem_raw);
+}
+
 template <typename T, int NB, typename Shape, int VW>
 void launch_shape_vw(const DevOps<T>& op, const T* Hp, const T* in, const T* y, T* out, T coef, long long n_items,
                      int wg_per_cu, hipStream_t stream) {
@@ -869,6 +950,98 @@ void launch_rhs_mfma_multi(const InstDesc<T>* desc, int n_inst, int nb, int vw, 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw std::runtime_error(std::string("mfma multi kernel: ") + hipGetErrorString(e));
 }
+
+template <typename T>
+size_t fused_lds_bytes(int nb) {
+  const size_t DP = 16 * static_cast<size_t>(nb);
+  return (3 * DP * (DP + lds_pad(sizeof(T), nb)) + 4 * 64) * sizeof(T);
+}
+
+namespace {
+
+template <typename T, int W>
+void fused_attr_w(size_t lds) {
+  static size_t configured = 0;
+  if (lds > configured) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&rhs_mfma_fused_kernel<T, W>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
+      throw std::runtime_error("fused kernel: LDS attribute");
+    configured = lds;
+  }
+}
+
+template <typename T, int W>
+int fused_fit_w(size_t lds) {
+  auto kern = &rhs_mfma_fused_kernel<T, W>;
+  fused_attr_w<T, W>(lds);
+  int fit = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, reinterpret_cast<const void*>(kern), W * 64, lds) !=
+          hipSuccess ||
+      fit < 1)
+    fit = 1;
+  return fit;
+}
+
+template <typename T, int W>
+void fused_launch_w(const FusedClass* cls, int n_cls, const InstDesc<T>* desc, size_t lds, int grid, T coef,
+                    hipStream_t stream) {
+  fused_attr_w<T, W>(lds);
+  hipLaunchKernelGGL((rhs_mfma_fused_kernel<T, W>), dim3(static_cast<unsigned>(grid)), dim3(W * 64), lds, stream,
+                     cls, n_cls, desc, coef);
+}
+
+}  // namespace
+
+template <typename T>
+int fused_block_waves(const int* nbs, int n) {
+  int need = 0;
+  for (int i = 0; i < n; ++i) {
+    if (nbs[i] < 1 || nbs[i] > kFusedMaxNb) return 0;
+    need = std::max(need, class_waves<T>(nbs[i]));
+  }
+  if (need == 0) return 0;
+  if (sizeof(T) == 4) return need <= 5 ? 5 : 8;
+  return 10;
+}
+
+template <typename T>
+int fused_workgroups_per_cu(int waves, size_t lds) {
+  if constexpr (sizeof(T) == 4) {
+    if (waves == 5) return fused_fit_w<T, 5>(lds);
+    if (waves == 8) return fused_fit_w<T, 8>(lds);
+  } else {
+    if (waves == 10) return fused_fit_w<T, 10>(lds);
+  }
+  throw std::runtime_error("fused kernel: unsupported block width");
+}
+
+template <typename T>
+void launch_rhs_mfma_fused(const FusedClass* cls, int n_cls, const InstDesc<T>* desc, int waves, size_t lds,
+                           int grid, double coef, hipStream_t stream) {
+  if (grid <= 0 || n_cls <= 0) return;
+  const T c = static_cast<T>(coef);
+  if constexpr (sizeof(T) == 4) {
+    if (waves == 5) fused_launch_w<T, 5>(cls, n_cls, desc, lds, grid, c, stream);
+    else if (waves == 8) fused_launch_w<T, 8>(cls, n_cls, desc, lds, grid, c, stream);
+    else throw std::runtime_error("fused kernel: unsupported block width");
+  } else {
+    if (waves == 10) fused_launch_w<T, 10>(cls, n_cls, desc, lds, grid, c, stream);
+    else throw std::runtime_error("fused kernel: unsupported block width");
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw std::runtime_error(std::string("mfma fused kernel: ") + hipGetErrorString(e));
+}
+
+template size_t fused_lds_bytes<float>(int);
+template size_t fused_lds_bytes<double>(int);
+template int fused_block_waves<float>(const int*, int);
+template int fused_block_waves<double>(const int*, int);
+template int fused_workgroups_per_cu<float>(int, size_t);
+template int fused_workgroups_per_cu<double>(int, size_t);
+template void launch_rhs_mfma_fused<float>(const FusedClass*, int, const InstDesc<float>*, int, size_t, int, double,
+                                           hipStream_t);
+template void launch_rhs_mfma_fused<double>(const FusedClass*, int, const InstDesc<double>*, int, size_t, int,
+                                            double, hipStream_t);
 
 template void launch_rhs_mfma_multi<float>(const InstDesc<float>*, int, int, int, double, long long, hipStream_t);
 template void launch_rhs_mfma_multi<double>(const InstDesc<double>*, int, int, int, double, long long, hipStream_t);

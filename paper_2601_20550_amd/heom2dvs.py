@@ -141,6 +141,10 @@ _SIGS = {
     "heom_batch_propagate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int]),
     "heom_batch_response_2d": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(heom_grid), C.c_int,
                                          C.c_void_p]),
+    "heom_batch_set_launch": (C.c_int, [C.c_void_p, C.c_int]),
+    "heom_batch_get_launch": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
+    "heom_batch_set_graph_steps": (C.c_int, [C.c_void_p, C.c_int]),
+    "heom_batch_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p]),
     "heom_model_set_kernel": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "heom_model_set_graph_steps": (C.c_int, [C.c_void_p, C.c_int]),
     "heom_model_set_progress": (C.c_int, [C.c_void_p, _PROGRESS_FN, C.c_void_p, C.c_int]),
@@ -676,6 +680,32 @@ def heom_batch_response_2d(batch: Batch, rho_eqs, grid, precision="fp32"):
     optr = (C.c_void_p * len(outs))(*[o.ctypes.data for o in outs])
     _check(_lib.heom_batch_response_2d(batch.handle, rho, C.byref(g), _PREC[precision], optr))
     return [(o[0::2] + 1j * o[1::2]).reshape(n_t2, 2, grid["n1"], grid["n3"]) for o in outs]
+
+
+BATCH_LAUNCH = {"auto": 0, "per_class": 1, "single": 2}
+
+
+def heom_batch_set_launch(batch: Batch, launch: str):
+    """Launch form of the batch's RK4 stages: "per_class", "single" or "auto"."""
+    _check(_lib.heom_batch_set_launch(batch.handle, BATCH_LAUNCH[launch]))
+
+
+def heom_batch_get_launch(batch: Batch) -> str:
+    out = C.c_int()
+    _check(_lib.heom_batch_get_launch(batch.handle, C.byref(out)))
+    return {v: k for k, v in BATCH_LAUNCH.items()}[out.value]
+
+
+def heom_batch_set_graph_steps(batch: Batch, steps: int):
+    _check(_lib.heom_batch_set_graph_steps(batch.handle, int(steps)))
+
+
+def heom_batch_autotune(batch: Batch, precision="fp32", n_traj=1, reps=2):
+    """Times both launch forms; returns (form auto now resolves to,
+    {"per_class": ms per RK4 step, "single": ms per RK4 step or NaN})."""
+    ms = np.zeros(2)
+    _check(_lib.heom_batch_autotune(batch.handle, _PREC[precision], int(n_traj), int(reps), _ptr(ms)))
+    return heom_batch_get_launch(batch), {"per_class": float(ms[0]), "single": float(ms[1])}
 
 
 def heom_model_set_graph_steps(model, steps):

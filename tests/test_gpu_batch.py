@@ -167,3 +167,139 @@ def test_batch_six_row_block_class_and_wide_mode_rejected():
     with pytest.raises(P.heom2dvs.HeomError) as e:
         P.heom_batch_create([P.heom_model_build(wide)])
     assert e.value.code == P.heom2dvs.HEOM_ERR_PARAM
+
+
+def _class_instances(with_nb4=True):
+    """One instance per size class the single launch covers: d = 6, 25 and 80
+    from the uneven batch, and the three-mode model kept at (4, 4, 3) and
+    (4, 4, 4) levels (d = 48 and 64) at depth 1."""
+    ps = [p for p in _instances()]
+    base = w.cfg3()[0]
+    for keep in ((4, 4, 3), (4, 4, 4)) if with_nb4 else ((4, 4, 3),):
+        p = dict(base)
+        p["modes"] = [dict(md) for md in base["modes"]]
+        p["depth"] = 1
+        for md, k in zip(p["modes"], keep):
+            md["n_keep"] = k
+        ps.append(p)
+    return ps
+
+
+def _random_states(models, os_, prec, seed):
+    xs, states = [], []
+    for i, (m, o) in enumerate(zip(models, os_)):
+        nt = 1 + i % 3
+        x = w.random_hierarchy(nt, len(o.hier), o.d, seed=seed + i, scale_by_depth=0.3 ** o.hier.n.sum(1))
+        s = P.State(m, nt, prec)
+        s.upload(x)
+        xs.append(x)
+        states.append(s)
+    return xs, states
+
+
+@pytest.mark.parametrize("with_nb4", [True, False])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_single_launch_parity(with_nb4, prec, tol, adjoint):
+    # one launch per RK4 stage over five (or four) size classes: workgroups
+    # split among the classes, narrower classes leaving the extra waves idle;
+    # against the oracle and against the per-class launches
+    ps = _class_instances(with_nb4)
+    os_ = [om.build(p) for p in ps]
+    models = [P.heom_model_build(p) for p in ps]
+    xs, single = _random_states(models, os_, prec, 90)
+    _, per_class = _random_states(models, os_, prec, 90)
+    b = P.heom_batch_create(models)
+    P.heom_batch_set_launch(b, "single")
+    assert P.heom_batch_get_launch(b) == "single"
+    P.heom_batch_propagate(b, single, 3, adjoint)
+    P.heom_batch_set_launch(b, "per_class")
+    P.heom_batch_propagate(b, per_class, 3, adjoint)
+    for i, (o, x, s, c) in enumerate(zip(os_, xs, single, per_class)):
+        ref = np.stack([oh.propagate(o, x[t], 3, adjoint=adjoint) for t in range(x.shape[0])])
+        got = s.download()
+        assert _relerr(got, ref) < tol, (i, o.d)
+        assert _relerr(got, c.download()) < (1e-12 if prec == "fp64" else 2e-6), (i, o.d)
+
+
+def test_single_launch_response_matches_per_class(instances):
+    ps, os_ = instances
+    grid = {"n1": 3, "n3": 3, "steps_per_sample": 4, "t2_steps": [0, 5]}
+    models = [P.heom_model_build(p) for p in ps]
+    rhos = []
+    for m, o in zip(models, os_):
+        s = P.State(m, 1, "fp64")
+        s.upload(oh.propagate(o, oh.ground_state_hierarchy(o), 20)[None])
+        rhos.append(s)
+    b = P.heom_batch_create(models)
+    ref = P.heom_batch_response_2d(b, rhos, grid, "fp64")
+    P.heom_batch_set_launch(b, "single")
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-4)):
+        got = P.heom_batch_response_2d(b, rhos, grid, prec)
+        for g, r in zip(got, ref):
+            assert _relerr(g, r) < tol
+
+
+@pytest.mark.parametrize("launch", ["per_class", "single"])
+def test_batch_graph_replays_match_direct_launches(instances, launch):
+    # graph_steps = 2: a 7-step call replays its captured graph three times
+    # and finishes with one direct step; three calls in a row with eager
+    # work (traces) and synchronisations between them, every result compared
+    # with direct launches bit for bit; then a response whose t1 / t3 / t2
+    # loops replay one captured graph between the dipole and pairing launches
+    import torch
+    ps, os_ = instances
+    models = [P.heom_model_build(p) for p in ps]
+    _, sg = _random_states(models, os_, "fp32", 120)
+    _, sd = _random_states(models, os_, "fp32", 120)
+    bg, bd = P.heom_batch_create(models), P.heom_batch_create(models)
+    for b in (bg, bd):
+        P.heom_batch_set_launch(b, launch)
+    P.heom_batch_set_graph_steps(bg, 2)
+    for _ in range(3):
+        P.heom_batch_propagate(bg, sg, 7)
+        P.heom_batch_propagate(bd, sd, 7)
+        for m, a, c in zip(models, sg, sd):
+            assert np.array_equal(P.heom_trace(m, a), P.heom_trace(m, c))
+        torch.cuda.synchronize()
+        for a, c in zip(sg, sd):
+            assert np.array_equal(a.download(), c.download())
+    grid = {"n1": 3, "n3": 3, "steps_per_sample": 2, "t2_steps": [0, 4]}
+    rhos = []
+    for m, o in zip(models, os_):
+        s = P.State(m, 1, "fp64")
+        s.upload(oh.propagate(o, oh.ground_state_hierarchy(o), 20)[None])
+        rhos.append(s)
+    rg = P.heom_batch_response_2d(bg, rhos, grid, "fp32")
+    rd = P.heom_batch_response_2d(bd, rhos, grid, "fp32")
+    for a, c in zip(rg, rd):
+        assert np.array_equal(a, c)
+
+
+def test_batch_autotune_picks_the_faster_form(instances):
+    ps, os_ = instances
+    models = [P.heom_model_build(p) for p in ps]
+    b = P.heom_batch_create(models)
+    assert P.heom_batch_get_launch(b) == "per_class"
+    chosen, ms = P.heom_batch_autotune(b, "fp32", n_traj=2, reps=2)
+    assert np.isfinite(ms["per_class"]) and np.isfinite(ms["single"])
+    assert chosen == ("single" if ms["single"] < ms["per_class"] else "per_class")
+    assert P.heom_batch_get_launch(b) == chosen
+    xs, st = _random_states(models, os_, "fp32", 140)
+    P.heom_batch_propagate(b, st, 2)
+    for o, x, s in zip(os_, xs, st):
+        ref = np.stack([oh.propagate(o, x[t], 2) for t in range(x.shape[0])])
+        assert _relerr(s.download(), ref) < 1e-5
+    # a d = 96 instance (six row blocks) keeps the per-class form only
+    base = w.cfg3()[0]
+    p = dict(base)
+    p["modes"] = [dict(md) for md in base["modes"]]
+    p["depth"] = 1
+    for md, k in zip(p["modes"], (4, 4, 6)):
+        md["n_keep"] = k
+    bw = P.heom_batch_create([models[0], P.heom_model_build(p)])
+    with pytest.raises(P.heom2dvs.HeomError) as e:
+        P.heom_batch_set_launch(bw, "single")
+    assert e.value.code == P.heom2dvs.HEOM_ERR_PARAM
+    chosen, ms = P.heom_batch_autotune(bw, "fp32", n_traj=1, reps=1)
+    assert chosen == "per_class" and np.isnan(ms["single"])
