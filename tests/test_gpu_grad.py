@@ -170,6 +170,44 @@ def test_vjp_three_modes_sampled_entries():
     assert np.max(np.abs(val - ref)) < 1e-6 * scale, (val, ref)
 
 
+def test_gradient_model_derivative_along_a_random_direction():
+    # The full gradient model (three modes, depth 6: 5005 ADOs of 80 x 80,
+    # t2 in {0, 100 fs}) on a 2 x 2 grid, rho held fixed: the parameter
+    # gradient (adjoint sweep, then the chain through the build) projected on
+    # a random direction v equals the central difference (step 1e-5) of the
+    # FP64 responses along v.  This is the derivative identity, which holds at
+    # any size; the oracle cannot run this model, and the comparisons against
+    # the oracle's differences run the same code at depth 1 and on the reduced
+    # gradient workload above.
+    params, g5, _ = w.cfg5()
+    assert params["depth"] == 6
+    grid = {"n1": 2, "n3": 2, "steps_per_sample": 10, "t2_steps": list(g5["t2_steps"])}
+    m = P.heom_model_build(params)
+    assert (m.n_ado, m.d) == (5005, 80)
+    rho = P.State(m, 1, "fp64")
+    rho.set_ground()
+    P.heom_propagate(m, rho, 200)
+    W = _random_W(grid, 11)
+    g = P.heom_response_2d_vjp(m, rho, grid, W, stationary=False)
+    dirs = w.theta_directions(params)
+    gt = P.heom_params_vjp(params, dirs, g)
+    assert gt.shape == (12,) and np.isfinite(gt).all()
+    rh = rho.download()
+    v = np.random.default_rng(12).standard_normal(len(dirs))
+    v /= np.linalg.norm(v)
+
+    def J(t):
+        mm = P.heom_model_build(w.apply_theta(params, 1.0 + t * v))
+        r = P.State(mm, 1, "fp64")
+        r.upload(rh)
+        return float(np.sum(np.real(W * P.heom_response_2d(mm, r, grid, "fp64", "adjoint"))))
+
+    h = 1e-5
+    fd = (J(h) - J(-h)) / (2 * h)
+    scale = max(abs(fd), np.max(np.abs(gt)))
+    assert abs(float(gt @ v) - fd) < 1e-6 * scale, (float(gt @ v), fd, scale)
+
+
 def test_vjp_rejects_unsupported_models():
     params = w.cfg1()[0]
     params["modes"][0]["n_keep"] = 9          # single-mode dimension 9 > 8

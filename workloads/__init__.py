@@ -7,6 +7,8 @@ both sides read the same plain dictionaries and arrays produced here.
 
 from .configs import (  # noqa: F401
     FS_PER_TIME_UNIT,
+    FS_PER_TIME_UNIT_WATER,
+    WATER_OMEGA0_CM,
     cfg1,
     cfg2,
     cfg3,
@@ -22,5 +24,8 @@ from .configs import (  # noqa: F401
     fs_to_steps,
     response_grid,
     with_brownian_baths,
+    water_beta,
+    water_three_mode,
+    water_two_mode,
 )
 from .states import random_hierarchy  # noqa: F401

@@ -255,6 +255,80 @@ def theta_directions(params):
     return out
 
 
+# ---------------------------------------------------------------------------
+# The paper's water models (Sec. IV, Tables I-III).  Their energy unit is
+# omega0 = 4000 cm^-1, so these dictionaries use it (not the 3470 cm^-1 of
+# the seeded workloads): time unit 1/omega0 = 1.3271 fs.
+
+WATER_OMEGA0_CM = 4000.0
+FS_PER_TIME_UNIT_WATER = 1.0e15 / (2.0 * math.pi * 2.99792458e10 * WATER_OMEGA0_CM)
+_CM_PER_KELVIN = 0.69503476   # k_B / (h c) in cm^-1 per K
+
+# Table rows: (nu_s [cm^-1], gamma_s/omega0, zeta~, V_LL~, V_SL~, g_{s^3}~, mu_s~, mu_ss~)
+_WATER_STRETCH_2 = (3520.0, 5.0e-3, 9.0, 0.0, 1.0, -0.5, 3.3, 1.2e-2)
+_WATER_BEND = (1710.0, 2.0e-2, 0.8, 0.0, 1.0, -0.7, 1.8, 0.0)
+_WATER_ASYM = (3570.0, 5.0e-3, 9.0, 0.0, 1.0, -0.5, 3.3, 1.2e-2)
+_WATER_SYM = (3470.0, 5.0e-3, 9.0, 0.0, 1.0, -0.5, 3.3, 1.2e-2)
+# Table III: (s, t, g_st~, g_s2t~, g_st2~, mu_st~) for 1-1', 1-2, 1'-2
+# (the garbled "-2,6 x 10^-2" read as -2.6e-2)
+_WATER_3_COUPLINGS = ((0, 1, -5.0e-3, 0.32, -4.2e-3, 0.0),
+                      (0, 2, 1.0e-7, -2.6e-2, 4.0e-4, 2.0e-3),
+                      (1, 2, -8.0e-4, 1.2e-1, -1.2e-2, 2.0e-3))
+
+
+def _water_mode(row, n_keep, K, n_basis):
+    """One mode from a table row.  Reading of the caption's normalisations:
+    each relation x~ = f x is applied as x = f x~ (the literal direction,
+    x = x~ / f, gives the bend a cubic barrier far below its zero-point
+    energy), with mu_0 and nu_0 read as omega0:
+    zeta = (omega0/omega_s)^2 zeta~, V_LL = (omega_s/omega0) V_LL~,
+    V_SL = V_SL~, g3 = (omega_s/omega0)^3 g~, mu_s = (omega0/omega_s) mu~,
+    mu_ss = (omega0/omega_s)^2 mu_ss~.  No quartic term (the tables give
+    none)."""
+    nu, gam, zeta_t, vll_t, vsl_t, g3_t, mu_t, muss_t = row
+    r = nu / WATER_OMEGA0_CM
+    return {"omega": r, "g3": g3_t * r ** 3, "g4": 0.0, "V1": vll_t * r, "V2": vsl_t,
+            "zeta": zeta_t / r ** 2, "gamma": gam, "mu1": mu_t / r, "mu2": muss_t / r ** 2,
+            "n_basis": int(n_basis), "n_keep": int(n_keep), "K": int(K)}
+
+
+def water_beta(temperature_k: float = 300.0) -> float:
+    """beta hbar omega0 at the given temperature (the paper states none; 300 K
+    is assumed)."""
+    return WATER_OMEGA0_CM / (_CM_PER_KELVIN * float(temperature_k))
+
+
+def water_two_mode(n_levels: int = 4, K: int = 4, depth: int = 4, dt_fs: float = 0.25,
+                   temperature_k: float = 300.0, n_basis: int = 16):
+    """Table I: OH stretch (3520 cm^-1) and bend (1710 cm^-1), n_levels kept
+    eigenstates each, K Pade terms per mode, Fermi coupling g_{11'^2}~ = 0.2
+    and cross dipole 2e-3 (the caption's 1' labels read as the bend; no
+    bilinear or g_{1^2 1'} term).  Depth 4 at the paper's dt = 0.25 fs (depth 5
+    leaves the RK4 stability region for the fastest Pade rate; use
+    dt_fs = 0.2 there)."""
+    modes = [_water_mode(_WATER_STRETCH_2, n_levels, K, n_basis),
+             _water_mode(_WATER_BEND, n_levels, K, n_basis)]
+    couplings = [_coupling(0, 1, g_st=0.0, g_s2t=0.0, g_st2=0.2, mu_st=2.0e-3)]
+    return {"modes": modes, "couplings": couplings, "beta": water_beta(temperature_k),
+            "depth": int(depth), "decomp": "pade", "dt": float(dt_fs) / FS_PER_TIME_UNIT_WATER}
+
+
+def water_three_mode(n_levels: int = 4, K: int = 4, depth: int = 4, dt_fs: float = 0.25,
+                     temperature_k: float = 300.0, n_basis: int = 16):
+    """Tables II-III: asymmetric (3570) and symmetric (3470 cm^-1) stretches
+    and the bend (1710 cm^-1), n_levels kept eigenstates each (d = 64 at
+    four), K Pade terms per mode (M = 3 (K + 1) = 15 at K = 4), the
+    strong-coupling intermode terms of Table III.  Depth 4 (3876 ADOs) at
+    dt = 0.25 fs, as for the two-mode model."""
+    modes = [_water_mode(_WATER_ASYM, n_levels, K, n_basis),
+             _water_mode(_WATER_SYM, n_levels, K, n_basis),
+             _water_mode(_WATER_BEND, n_levels, K, n_basis)]
+    couplings = [_coupling(s, t, g_st=a, g_s2t=b, g_st2=c, mu_st=m)
+                 for s, t, a, b, c, m in _WATER_3_COUPLINGS]
+    return {"modes": modes, "couplings": couplings, "beta": water_beta(temperature_k),
+            "depth": int(depth), "decomp": "pade", "dt": float(dt_fs) / FS_PER_TIME_UNIT_WATER}
+
+
 def cfg5_small(seed: int = 0):
     """Reduced gradient workload (same layout as cfg5): two anharmonic modes
     kept at 3 and 2 levels (d = 6) with bilinear and Fermi couplings, K = 1 Pade
