@@ -111,10 +111,41 @@ def cpu_baseline(params, budget_s=30.0):
                                       f"thread ({dt_one:.1f} s each)"}}
 
 
+def batch_forms(P, torch, b, models, precision, n_traj=8, steps=5):
+    """RK4 steps of the whole batch with n_traj trajectories per instance (the
+    shape of the batched t2 propagation): the autotuner's choice, then ms per
+    step of per-class launches, one launch per stage, and the autotuned form
+    replayed from a captured graph."""
+    states = []
+    for m in models:
+        s = P.State(m, n_traj, precision)
+        s.set_ground()
+        states.append(s)
+    chosen, tune_ms = P.heom_batch_autotune(b, precision, n_traj=n_traj, reps=3)
+    out = {"trajectories_per_instance": n_traj, "steps": steps, "autotune_choice": chosen,
+           "autotune_ms_per_step": tune_ms}
+    items = n_traj * sum(m.n_ado for m in models)
+    for form, graph in (("per_class", 0), ("single", 0), (chosen, steps)):
+        P.heom_batch_set_launch(b, form)
+        P.heom_batch_set_graph_steps(b, graph)
+        P.heom_batch_propagate(b, states, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.heom_batch_propagate(b, states, steps)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        key = form + ("_graph" if graph else "")
+        out[key] = {"ms_per_step": dt * 1e3, "ado_updates_per_s": items / dt}
+    P.heom_batch_set_launch(b, "auto")
+    P.heom_batch_set_graph_steps(b, 0)
+    return out
+
+
 def multi_instance(P, torch, precision, stream, compare=False):
     """The uneven 64-instance batch (d = 6, 25, 80; 35..5005 ADOs; 64x64 grid at
-    t2 = 0): seconds for all 64 responses batched (one launch per size class
-    and RK4 stage) and one instance after another, and their agreement."""
+    t2 = 0): batched RK4 steps of 8 trajectories per instance in each launch
+    form, then seconds for all 64 responses batched (the autotuned form) and,
+    with compare, one instance after another, and their agreement."""
     import workloads as w
     insts = w.cfg4_instances()
     models = [P.heom_model_build(p, stream=stream) for p, _ in insts]
@@ -125,6 +156,7 @@ def multi_instance(P, torch, precision, stream, compare=False):
         r.set_ground()
         rhos.append(r)
     b = P.heom_batch_create(models)
+    forms = batch_forms(P, torch, b, models, precision)
     tiny = {"n1": 2, "n3": 2, "steps_per_sample": 1, "t2_steps": [0]}
     P.heom_batch_response_2d(b, rhos, tiny, precision)          # warm-up (code objects)
     torch.cuda.synchronize()
@@ -136,8 +168,9 @@ def multi_instance(P, torch, precision, stream, compare=False):
     # single-trajectory RK4 steps: t3 scan (adjoint) + one t1 scan per pathway
     ado_steps = sum(m.n_ado for m in models) * 3 * (n1 - 1) * sps
     out = {"instances": len(models), "grid": [n1, grid["n3"]], "t2": 0, "precision": precision,
-           "d_classes": sorted({m.d for m in models}), "s_batched": t_batch,
-           "ado_updates_per_s_batched": ado_steps / t_batch, "rho_eq": "ground state (timing only)"}
+           "d_classes": sorted({m.d for m in models}), "launch_form": P.heom_batch_get_launch(b),
+           "s_batched": t_batch, "ado_updates_per_s_batched": ado_steps / t_batch,
+           "rho_eq": "ground state (timing only)", "batched_trajectories": forms}
     if compare:
         t0 = time.perf_counter()
         Rs = [P.heom_response_2d(m, r, grid, precision, "adjoint") for m, r in zip(models, rhos)]

@@ -411,11 +411,12 @@ int heom_batch_response_2d(heom_batch* batch, const heom_state* const* rho_eq, c
  *   HEOM_BATCH_PER_CLASS: one persistent launch per size class and stage.
  *   HEOM_BATCH_SINGLE   : one persistent launch per stage over every class:
  *                         its workgroups are split among the classes in
- *                         proportion to each class's work (matrices x cost
- *                         per matrix, measured by heom_batch_autotune, else
- *                         a cost model growing as nb^2 (nb + 1)); a
- *                         workgroup runs the item code of its class.  Needs
- *                         every d <= 80 (HEOM_ERR_PARAM otherwise).
+ *                         proportion to matrices x time per matrix per
+ *                         workgroup (measured by heom_batch_autotune, else
+ *                         a model 4 + nb (nb + 1)); a workgroup runs the
+ *                         item code of its class, with the LDS and width of
+ *                         the widest class.  Needs every d <= 80
+ *                         (HEOM_ERR_PARAM otherwise).
  *   HEOM_BATCH_AUTO     : the form heom_batch_autotune chose, per class
  *                         before any tuning (the default).
  * Both forms compute the same stages (results equal to rounding order). */
@@ -495,11 +496,14 @@ int heom_model_set_graph_steps(heom_model* model, int steps);
  * batches and pathways of the call) and the GMRES operator applications of
  * heom_equilibrate_krylov / heom_stationary_refine and of the stationary
  * term of heom_response_2d_vjp ("stationary solve": steps of all
- * applications, of at most max_applies x steps_per_apply) synchronise the
- * model's stream every `every_steps` RK4 steps (at the next application
- * boundary for the stationary solve) and call fn(phase, steps_done,
- * steps_total, ctx) on the calling thread.  fn = NULL or every_steps <= 0
- * turns it off (default).  The callback must not call into this library. */
+ * applications, of at most max_applies x steps_per_apply), and the adjoint
+ * sweeps of heom_response_2d_vjp ("gradient sweep": adjoint RK4 steps over
+ * the t2 chunks and pathways, the t1 scans and the detection scan; reported
+ * at the end of a checkpoint segment) synchronise the model's stream every
+ * `every_steps` RK4 steps (at the next application or segment boundary) and
+ * call fn(phase, steps_done, steps_total, ctx) on the calling thread.
+ * fn = NULL or every_steps <= 0 turns it off (default).  The callback must
+ * not call into this library. */
 typedef void (*heom_progress_fn)(const char* phase, long long done, long long total, void* ctx);
 int heom_model_set_progress(heom_model* model, heom_progress_fn fn, void* ctx, int every_steps);
 /* Times every kernel variant that applies to the model (variants that would

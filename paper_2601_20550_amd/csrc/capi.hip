@@ -895,9 +895,11 @@ struct heom_batch {
 
 namespace {
 
-// Relative cost of one matrix of size class nb when nothing was measured:
-// matrix-core work grows as nb^3, neighbour and staging traffic as nb^2.
-double default_class_cost(int nb) { return static_cast<double>(nb) * nb * (nb + 1); }
+// Relative time of one matrix per workgroup in size class nb when nothing
+// was measured: matrix-core work grows as nb^3, neighbour and staging traffic
+// as nb^2, and a workgroup has nb waves (per-matrix latency grows about as
+// nb (nb + 1)), plus a fixed part for the item's global loads and barriers.
+double default_class_cost(int nb) { return 4.0 + static_cast<double>(nb) * (nb + 1); }
 
 // Descriptor sets of one batched propagation: per size class and for both
 // generators, the four stage role assignments of the Horner RK4 step.  With
@@ -1136,7 +1138,11 @@ void batch_autotune(heom_batch* b, int n_traj, int reps, double* ms_out) {
         heom::launch_rhs_mfma_multi<T>(c.desc[0][s4].template as<heom::InstDesc<T>>(), c.n_inst, c.nb, c.vw,
                                        coef[s4], c.n_items, b->stream);
     hip_check(hipEventRecord(guard.e1, b->stream), "event record");
-    b->class_cost[c.nb] = elapsed() / (4.0 * reps * static_cast<double>(std::max<long long>(1, c.n_items)));
+    // time per matrix per workgroup: what sets how many of the single
+    // launch's workgroups the class needs to finish with the others
+    const double grid_c = static_cast<double>(heom::rhs_mfma_multi_grid<T>(c.nb, c.vw, c.n_items));
+    b->class_cost[c.nb] =
+        elapsed() * grid_c / (4.0 * reps * static_cast<double>(std::max<long long>(1, c.n_items)));
   }
   hip_check(hipEventRecord(guard.e0, b->stream), "event record");
   pc.direct_steps(b, reps, false, b->stream);
@@ -1402,6 +1408,7 @@ struct GradCtx {
   // sweep buffers
   DevBuf S, Ob, Zp;
   long long cap_S = 0, cap_O = 0;
+  Progress* pr = nullptr;  // adjoint steps swept (heom_model_set_progress)
 };
 
 DevBuf upload_coef(const std::vector<double>& c, hipStream_t st) { return upload_vec(c, st); }
@@ -1518,6 +1525,15 @@ void sweep(GradCtx& g, const double* S0, double* O, int nt, int n, bool stored_a
     stage<double>(m, go, Ob + 3 * N, Ob, Ob, h * h * h * h / 24.0, nt);
   }
   hip_check(hipMemcpyAsync(O, Ob, N * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+  if (g.pr) {
+    Progress& pr = *g.pr;
+    pr.done += n;
+    if (pr.on() && pr.done >= pr.next) {
+      hip_check(hipStreamSynchronize(st), "sync");
+      m->progress_fn(pr.phase, pr.done, pr.total, m->progress_ctx);
+      pr.next = (pr.done / m->progress_every + 1) * m->progress_every;
+    }
+  }
 }
 
 void copy_dev(double* dst, const double* src, long long n, hipStream_t st) {
@@ -1571,6 +1587,10 @@ void response_vjp(heom_model* m, const heom_state* rho_eq, const heom_grid& gr, 
   const size_t fr = free_device_bytes();
   const size_t budget = fr > (size_t(2) << 30) ? fr - (size_t(2) << 30) : 0;
   const int nc = static_cast<int>(std::max<long long>(1, std::min<long long>(n1, budget / per_traj)));
+  // adjoint RK4 steps of all sweeps: t2 per chunk and pathway, the t1 scans, the detection scan
+  Progress prog(m, "gradient sweep",
+                2LL * ((n1 + nc - 1) / nc) * T_max + 2LL * (n1 - 1) * sps + static_cast<long long>(n3 - 1) * sps);
+  g.pr = &prog;
   const int pw_d[2][2] = {{HEOM_OP_MU_MINUS, HEOM_OP_MU_PLUS}, {HEOM_OP_MU_PLUS, HEOM_OP_MU_MINUS}};
   for (int P = 0; P < 2; ++P) {
     const int D1 = pw_d[P][0], D2 = pw_d[P][1];

@@ -103,6 +103,9 @@ struct InstDesc {
 template <typename T>
 void launch_rhs_mfma_multi(const InstDesc<T>* desc, int n_inst, int nb, int vw, double coef, long long n_items,
                            hipStream_t stream);
+// Workgroups that launch uses for one class.
+template <typename T>
+long long rhs_mfma_multi_grid(int nb, int vw, long long n_items);
 
 // One size class of a single-launch multi-class stage: its instances are
 // desc[inst_first, inst_first + n_inst) (items numbered from 0 within the

@@ -896,8 +896,9 @@ void launch_rhs_mfma(const DevOps<T>& op, const T* Hp, const T* in, const T* y, 
 
 namespace {
 
+// persistent grid of the per-class launch
 template <typename T, int NB, int VW>
-void launch_multi_nb(const InstDesc<T>* desc, int n_inst, T coef, long long n_items, hipStream_t stream) {
+long long multi_grid_nb(long long n_items) {
   const size_t lds = Lds<T, NB>::bytes;
   constexpr int MINW = minw_of<T, NB>();
   auto kern = &rhs_mfma_multi_kernel<T, NB, MINW, VW>;
@@ -917,6 +918,15 @@ void launch_multi_nb(const InstDesc<T>* desc, int n_inst, T coef, long long n_it
     wg = fit;
   long long grid = static_cast<long long>(cu_count()) * wg;
   if (grid > n_items) grid = n_items;
+  return grid;
+}
+
+template <typename T, int NB, int VW>
+void launch_multi_nb(const InstDesc<T>* desc, int n_inst, T coef, long long n_items, hipStream_t stream) {
+  const size_t lds = Lds<T, NB>::bytes;
+  constexpr int MINW = minw_of<T, NB>();
+  auto kern = &rhs_mfma_multi_kernel<T, NB, MINW, VW>;
+  const long long grid = multi_grid_nb<T, NB, VW>(n_items);
   hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(NB * 64 * wpr_of<T, NB>()), lds, stream, desc,
                      n_inst, coef,
                      n_items);
@@ -931,6 +941,21 @@ void launch_multi_vw(const InstDesc<T>* desc, int n_inst, int vw, T coef, long l
 }
 
 }  // namespace
+
+template <typename T>
+long long rhs_mfma_multi_grid(int nb, int vw, long long n_items) {
+  const bool full = vw == 16 / static_cast<int>(sizeof(T));
+  switch (nb) {
+    case 1: return full ? multi_grid_nb<T, 1, 16 / sizeof(T)>(n_items) : multi_grid_nb<T, 1, 1>(n_items);
+    case 2: return full ? multi_grid_nb<T, 2, 16 / sizeof(T)>(n_items) : multi_grid_nb<T, 2, 1>(n_items);
+    case 3: return full ? multi_grid_nb<T, 3, 16 / sizeof(T)>(n_items) : multi_grid_nb<T, 3, 1>(n_items);
+    case 4: return full ? multi_grid_nb<T, 4, 16 / sizeof(T)>(n_items) : multi_grid_nb<T, 4, 1>(n_items);
+    case 5: return full ? multi_grid_nb<T, 5, 16 / sizeof(T)>(n_items) : multi_grid_nb<T, 5, 1>(n_items);
+    case 6: return full ? multi_grid_nb<T, 6, 16 / sizeof(T)>(n_items) : multi_grid_nb<T, 6, 1>(n_items);
+    case 7: return full ? multi_grid_nb<T, 7, 16 / sizeof(T)>(n_items) : multi_grid_nb<T, 7, 1>(n_items);
+    default: throw std::runtime_error("multi-instance MFMA kernel supports ceil(d/16) <= 7");
+  }
+}
 
 template <typename T>
 void launch_rhs_mfma_multi(const InstDesc<T>* desc, int n_inst, int nb, int vw, double coef, long long n_items,
@@ -1043,6 +1068,8 @@ template void launch_rhs_mfma_fused<float>(const FusedClass*, int, const InstDes
 template void launch_rhs_mfma_fused<double>(const FusedClass*, int, const InstDesc<double>*, int, size_t, int,
                                             double, hipStream_t);
 
+template long long rhs_mfma_multi_grid<float>(int, int, long long);
+template long long rhs_mfma_multi_grid<double>(int, int, long long);
 template void launch_rhs_mfma_multi<float>(const InstDesc<float>*, int, int, int, double, long long, hipStream_t);
 template void launch_rhs_mfma_multi<double>(const InstDesc<double>*, int, int, int, double, long long, hipStream_t);
 
