@@ -94,119 +94,108 @@ __global__ __launch_bounds__(GT) void combine_kernel(const double* __restrict__ 
 }
 
 // ---------------------------------------------------------- gemm_grad ------
-// partial[blockIdx.x][i][j] += Re(f * sum_items (u z^T - z^T u)[i][j]).
-// Workgroup: 16 x 16 threads, thread (ti, tj) owns outputs i = ti + 16a,
-// j = tj + 16b (a, b < NB).  f * u is staged in LDS (DP x (DP+1), zero padded),
-// z passes through LDS in 16-column (u z^T) and 16-row (z^T u) slabs.
+// partial[blockIdx.x][i][j] += Re(f * sum_items (u z^T - z^T u)[i][j]) on the
+// FP64 matrix cores (v_mfma_f64_16x16x4: A[i][k] at lane i + 16 k, B[k][j] at
+// lane j + 16 k, accumulator element r at row lq + 4 r, column lr).  NB waves
+// (d <= 16 NB): the item's z is staged in LDS (zero padded to DP x DP);
+// wave w accumulates the tiles (w, tj) of Re(f u z^T), A = f u from global
+// memory (rows 16 w ..), B = z^T from LDS, and the tiles (ti, w) of
+// Re(z^T f u), A = z^T from LDS, B = f u from global memory (columns 16 w ..).
+// The two sums meet in LDS once per launch.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 template <int NB>
-__global__ __launch_bounds__(GT) void gemm_grad_kernel(const double* __restrict__ u, const double* __restrict__ z,
-                                                       long long n_items, int d, double f_re, double f_im,
-                                                       double* __restrict__ partial) {
+__global__ __launch_bounds__(NB * 64) void gemm_grad_kernel(const double* __restrict__ u, const double* __restrict__ z,
+                                                            long long n_items, int d, double f_re, double f_im,
+                                                            double* __restrict__ partial) {
   constexpr int DP = 16 * NB;
-  constexpr int LD = DP + 1;
+  constexpr int LDZ = DP + 1;
+  constexpr int NT = NB * 64;
   HIP_DYNAMIC_SHARED(double, lds);
-  double* fur = lds;
-  double* fui = fur + DP * LD;
-  double* zr = fui + DP * LD;
-  constexpr int ZB = (DP * 17 > 16 * LD) ? DP * 17 : 16 * LD;
-  double* zi = zr + ZB;
-  const int tid = threadIdx.x, ti = tid / 16, tj = tid % 16;
+  double* zr = lds;
+  double* zi = lds + DP * LDZ;
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
   const long long dd = static_cast<long long>(d) * d;
-  double acc[NB][NB];
+  f64x4 acc1[NB], acc2[NB];
 #pragma unroll
-  for (int a = 0; a < NB; ++a)
-#pragma unroll
-    for (int b = 0; b < NB; ++b) acc[a][b] = 0.0;
-  for (int e = tid; e < DP * LD; e += GT) {
-    fur[e] = 0.0;
-    fui[e] = 0.0;
+  for (int t = 0; t < NB; ++t) {
+    acc1[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    acc2[t] = f64x4{0.0, 0.0, 0.0, 0.0};
   }
+  for (int e = tid; e < 2 * DP * LDZ; e += NT) lds[e] = 0.0;
+  const int ia = 16 * w + lr;  // row of f u in the first sum, column in the second
   for (long long it = blockIdx.x; it < n_items; it += gridDim.x) {
     const double* U = u + it * 2 * dd;
     const double* Z = z + it * 2 * dd;
-    __syncthreads();
-    for (int e = tid; e < d * d; e += GT) {
+    __syncthreads();  // previous item's LDS reads are complete
+    for (int e = tid; e < d * d; e += NT) {
       const int x = e / d, y = e - x * d;
-      const double ur = U[e], ui = U[e + dd];
-      fur[x * LD + y] = f_re * ur - f_im * ui;
-      fui[x * LD + y] = f_re * ui + f_im * ur;
+      zr[x * LDZ + y] = Z[e];
+      zi[x * LDZ + y] = Z[e + dd];
     }
-    // u z^T: sum over columns c
-    for (int c0 = 0; c0 < d; c0 += 16) {
-      __syncthreads();
-      for (int e = tid; e < DP * 16; e += GT) {
-        const int j = e / 16, cc = e - j * 16, c = c0 + cc;
-        double vr = 0.0, vi = 0.0;
-        if (j < d && c < d) {
-          vr = Z[j * d + c];
-          vi = Z[j * d + c + dd];
-        }
-        zr[j * 17 + cc] = vr;
-        zi[j * 17 + cc] = vi;
+    __syncthreads();
+    // Re(f u z^T): sum over columns c of u and z
+#pragma unroll 2
+    for (int c0 = 0; c0 < DP; c0 += 4) {
+      const int c = c0 + lk;
+      double ur = 0.0, ui = 0.0;
+      if (ia < d && c < d) {
+        ur = U[ia * d + c];
+        ui = U[ia * d + c + dd];
       }
-      __syncthreads();
-      const int cm = min(16, d - c0);
-      for (int cc = 0; cc < cm; ++cc) {
-        double ar[NB], ai[NB], br[NB], bi[NB];
+      const double ar = f_re * ur - f_im * ui, ai = -(f_re * ui + f_im * ur);
 #pragma unroll
-        for (int a = 0; a < NB; ++a) {
-          ar[a] = fur[(ti + 16 * a) * LD + c0 + cc];
-          ai[a] = fui[(ti + 16 * a) * LD + c0 + cc];
-          br[a] = zr[(tj + 16 * a) * 17 + cc];
-          bi[a] = zi[(tj + 16 * a) * 17 + cc];
-        }
-#pragma unroll
-        for (int a = 0; a < NB; ++a)
-#pragma unroll
-          for (int b = 0; b < NB; ++b) acc[a][b] += ar[a] * br[b] - ai[a] * bi[b];
+      for (int tj = 0; tj < NB; ++tj) {
+        const int j = 16 * tj + lr;
+        acc1[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, zr[j * LDZ + c], acc1[tj], 0, 0, 0);
+        acc1[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, zi[j * LDZ + c], acc1[tj], 0, 0, 0);
       }
     }
-    // - z^T u: sum over rows x
-    for (int x0 = 0; x0 < d; x0 += 16) {
-      __syncthreads();
-      for (int e = tid; e < 16 * DP; e += GT) {
-        const int xx = e / DP, i = e - xx * DP, x = x0 + xx;
-        double vr = 0.0, vi = 0.0;
-        if (x < d && i < d) {
-          vr = Z[x * d + i];
-          vi = Z[x * d + i + dd];
-        }
-        zr[xx * LD + i] = vr;
-        zi[xx * LD + i] = vi;
+    // Re(z^T f u): sum over rows x of z and u
+#pragma unroll 2
+    for (int x0 = 0; x0 < DP; x0 += 4) {
+      const int x = x0 + lk;
+      double ur = 0.0, ui = 0.0;
+      if (x < d && ia < d) {
+        ur = U[x * d + ia];
+        ui = U[x * d + ia + dd];
       }
-      __syncthreads();
-      const int xm = min(16, d - x0);
-      for (int xx = 0; xx < xm; ++xx) {
-        double ar[NB], ai[NB], br[NB], bi[NB];
+      const double br = f_re * ur - f_im * ui, bi = -(f_re * ui + f_im * ur);
 #pragma unroll
-        for (int a = 0; a < NB; ++a) {
-          ar[a] = zr[xx * LD + ti + 16 * a];
-          ai[a] = zi[xx * LD + ti + 16 * a];
-          br[a] = fur[(x0 + xx) * LD + tj + 16 * a];
-          bi[a] = fui[(x0 + xx) * LD + tj + 16 * a];
-        }
-#pragma unroll
-        for (int a = 0; a < NB; ++a)
-#pragma unroll
-          for (int b = 0; b < NB; ++b) acc[a][b] -= ar[a] * br[b] - ai[a] * bi[b];
+      for (int ti = 0; ti < NB; ++ti) {
+        const int i = 16 * ti + lr;
+        acc2[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(zr[x * LDZ + i], br, acc2[ti], 0, 0, 0);
+        acc2[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(zi[x * LDZ + i], bi, acc2[ti], 0, 0, 0);
       }
     }
   }
+  // G = sum1 - sum2 in LDS: wave w owns tile row w of the first sum and tile
+  // column w of the second
+  __syncthreads();
+  double* G = lds;  // DP x LDZ
+#pragma unroll
+  for (int tj = 0; tj < NB; ++tj)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) G[(16 * w + lk + 4 * r) * LDZ + 16 * tj + lr] = acc1[tj][r];
+  __syncthreads();
+#pragma unroll
+  for (int ti = 0; ti < NB; ++ti)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) G[(16 * ti + lk + 4 * r) * LDZ + 16 * w + lr] -= acc2[ti][r];
+  __syncthreads();
   double* P = partial + static_cast<long long>(blockIdx.x) * dd;
-#pragma unroll
-  for (int a = 0; a < NB; ++a)
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int i = ti + 16 * a, j = tj + 16 * b;
-      if (i < d && j < d) P[i * d + j] += acc[a][b];
-    }
+  for (int e = tid; e < d * d; e += NT) {
+    const int i = e / d, j = e - i * d;
+    P[e] += G[i * LDZ + j];
+  }
 }
 
 template <int NB>
 size_t gemm_grad_lds() {
-  constexpr int DP = 16 * NB, LD = DP + 1;
-  constexpr int ZB = (DP * 17 > 16 * LD) ? DP * 17 : 16 * LD;
-  return sizeof(double) * (2 * DP * LD + 2 * ZB);
+  constexpr int DP = 16 * NB;
+  return sizeof(double) * 2 * DP * (DP + 1);
 }
 
 __global__ void reduce_parts_kernel(const double* __restrict__ partial, int n_parts, long long len,
@@ -313,11 +302,25 @@ __global__ __launch_bounds__(NBT) void nb_grad_kernel(GradOps g, int s, const do
           uvr += ubr[a] * vb;          // (u V)[x][y]
           uvi += ubi[a] * vb;
         }
+        // every neighbour element of this row is requested before any is
+        // used: one memory latency per row instead of one per neighbour
+        double zrq[MAXQ], ziq[MAXQ];
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) {
+          zrq[q] = 0.0;
+          ziq[q] = 0.0;
+          if (q < nq) {
+            const double* Zm = Zt + static_cast<long long>(qi[4 * q]) * 2 * dd;
+            zrq[q] = Zm[x * d + y];
+            ziq[q] = Zm[x * d + y + dd];
+          }
+        }
         double zLr = 0.0, zLi = 0.0, zRr = 0.0, zRi = 0.0;
         int kd = 0;
-        for (int q = 0; q < nq; ++q) {
-          const double* Zm = Zt + static_cast<long long>(qi[4 * q]) * 2 * dd;
-          const double zr_ = Zm[x * d + y], zi_ = Zm[x * d + y + dd];
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) {
+          if (q >= nq) break;
+          const double zr_ = zrq[q], zi_ = ziq[q];
           const double cr = qa[2 * q], ci = qa[2 * q + 1];
           zLr += cr * zr_ - ci * zi_;
           zLi += cr * zi_ + ci * zr_;
@@ -548,7 +551,7 @@ void gemm_grad_nb(const double* u, const double* z, long long n_items, int d, do
   const long long per_cu = std::max<long long>(1, (160 * 1024) / static_cast<long long>(lds));
   const long long grid = std::min<long long>({n_items, cus() * per_cu, grad_max_parts()});
   if (grid <= 0) return;
-  hipLaunchKernelGGL((gemm_grad_kernel<NB>), dim3(static_cast<unsigned>(grid)), dim3(GT), lds, stream, u, z,
+  hipLaunchKernelGGL((gemm_grad_kernel<NB>), dim3(static_cast<unsigned>(grid)), dim3(NB * 64), lds, stream, u, z,
                      n_items, d, fr, fi, partial);
   check("gemm_grad kernel");
 }
