@@ -12,8 +12,10 @@ with FP64 pairing) measured end to end for t2 = 0 and for the t2 set {0, 50 fs}
 (the batched t2 propagation in the timed region), the FP32 error of the t2 = 0
 spectrum against the FP64 path, the equilibration with its convergence flag, a
 short FP64 propagation leg with its own roofline, the roofline of the dominant
-kernel from HIP-event timings of its launches inside the timed region, and the
-CPU oracle's rate on a bounded sample (all cores and one core).
+kernel from HIP-event timings of its launches inside the timed region, the
+uneven multi-instance batch in each launch form, the reverse-mode gradient of
+the gradient workload's depth-6 model on a 2 x 2 grid, and the CPU oracle's
+rate on a bounded sample (all cores and one core).
 """
 
 from __future__ import annotations
@@ -100,7 +102,7 @@ def cpu_baseline(params, budget_s=30.0):
         dt = (time.perf_counter() - t0) / n_rhs
         return len(o.hier) / (4.0 * dt), n_rhs, dt  # one ADO-update = one RK4 step = 4 RHS
 
-    r_all, n_all, dt_all = rate(budget_s / 3, 3)
+    r_all, n_all, dt_all = rate(budget_s / 3, 2)
     with threadpool_limits(1):
         r_one, n_one, dt_one = rate(budget_s / 3, 1)
     return {"value": r_all, "unit": "ADO-updates/s", "cores": int(cores), "kind": "oracle",
@@ -142,14 +144,19 @@ def batch_forms(P, torch, b, models, precision, n_traj=8, steps=5):
 
 
 def multi_instance(P, torch, precision, stream, compare=False):
-    """The uneven 64-instance batch (d = 6, 25, 80; 35..5005 ADOs; 64x64 grid at
-    t2 = 0): batched RK4 steps of 8 trajectories per instance in each launch
-    form, then seconds for all 64 responses batched (the autotuned form) and,
-    with compare, one instance after another, and their agreement."""
+    """The uneven 64-instance batch (d = 6, 25, 80; 35..5005 ADOs; t2 = 0):
+    batched RK4 steps of 8 trajectories per instance in each launch form, then
+    seconds for all 64 responses batched (the autotuned form; 16 x 16 samples
+    of the workload's 64 x 64 grid spacing) and, with compare, one instance
+    after another, and their agreement."""
     import workloads as w
     insts = w.cfg4_instances()
     models = [P.heom_model_build(p, stream=stream) for p, _ in insts]
-    grid = insts[0][1]
+    # the 64 x 64 grid of the workload, reduced to 16 x 16 samples at the
+    # same spacing to keep the default run short (the scans are 150 instead
+    # of 630 RK4 steps)
+    grid = dict(insts[0][1])
+    grid["n1"] = grid["n3"] = 16
     rhos = []
     for m in models:
         r = P.State(m, 1, "fp64")
@@ -184,20 +191,25 @@ def multi_instance(P, torch, precision, stream, compare=False):
 
 
 def gradient_timing(P, torch, stream):
-    """Reverse-mode gradient (FP64) of a random linear functional of the responses
-    of the three-mode model reduced to depth 3 (220 ADOs), 16 x 16 grid every 10
-    steps, t2 in {0, 65 steps}: seconds for the forward responses and for the
-    vjp (rho held fixed; rho = 200 RK4 steps from the ground state)."""
+    """Reverse-mode gradient (FP64) of a random linear functional of the
+    responses of the gradient workload's model (three modes, depth 6: 5005 ADOs
+    of 80 x 80; t2 in {0, 100 fs}) on a 2 x 2 grid every 10 steps, rho held
+    fixed (200 RK4 steps from the ground state): seconds for the forward
+    responses, for the vjp (operator gradients) and for the chain to the 12
+    fitted parameters.  One t1 and one t3 sample (t1 = t3 = 0), so the cost is
+    the t2 propagation of both pathways and its adjoint sweep; the 64 x 64 grid
+    propagates 64 trajectories per pathway through t2 instead of one."""
     import workloads as w
-    params, _, _ = w.cfg5()
-    params["depth"] = 3
-    grid = {"n1": 16, "n3": 16, "steps_per_sample": 10, "t2_steps": [0, 65]}
+    params, g5, _ = w.cfg5()
+    grid = {"n1": 1, "n3": 1, "steps_per_sample": 10, "t2_steps": list(g5["t2_steps"])}
     m = P.heom_model_build(params, stream=stream)
     rho = P.State(m, 1, "fp64")
     rho.set_ground()
     P.heom_propagate(m, rho, 200)
     P.heom_response_2d(m, rho, {"n1": 2, "n3": 2, "steps_per_sample": 1, "t2_steps": [0]}, "fp64",
                        "adjoint")
+    P.heom_model_set_progress(m, lambda ph, done, tot: print(f"gradient leg, {ph}: {done}/{tot} RK4 steps",
+                                                             file=sys.stderr, flush=True), 200)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     R = P.heom_response_2d(m, rho, grid, "fp64", "adjoint")
@@ -208,10 +220,14 @@ def gradient_timing(P, torch, stream):
     g = P.heom_response_2d_vjp(m, rho, grid, W, stationary=False)
     torch.cuda.synchronize()
     t_vjp = time.perf_counter() - t0
-    return {"model": "3-mode, depth 3 (220 ADOs), d = 80", "grid": [16, 16], "t2_steps": [0, 65],
-            "precision": "fp64", "s_forward_responses": t_fwd, "s_vjp": t_vjp,
-            "vjp_over_forward": t_vjp / t_fwd,
-            "finite": bool(np.isfinite(g["H"]).all() and np.isfinite(g["mu"]).all())}
+    P.heom_model_set_progress(m, None)
+    t0 = time.perf_counter()
+    gt = P.heom_params_vjp(params, w.theta_directions(params), g)
+    t_chain = time.perf_counter() - t0
+    return {"model": "3-mode, depth 6 (5005 ADOs), d = 80, 12 parameters", "grid": [1, 1],
+            "t2_steps": grid["t2_steps"], "precision": "fp64", "s_forward_responses": t_fwd, "s_vjp": t_vjp,
+            "s_parameter_chain": t_chain, "vjp_over_forward": t_vjp / t_fwd,
+            "finite": bool(np.isfinite(gt).all())}
 
 
 def fp64_leg(P, torch, m, steps, flops_per_traj):
@@ -433,18 +449,30 @@ def main():
         line["roofline"]["traffic_unit"] = "bytes per launch (HBM, calibrated rocprofv3 counters)"
         line["roofline"]["hbm_GBs_at_traffic"] = line["roofline"]["traffic"] / avg_launch_s / 1e9
 
+    t_leg = time.perf_counter()
+
+    def leg_done(name):
+        nonlocal t_leg
+        print(f"{name} leg done in {time.perf_counter() - t_leg:.1f} s", file=sys.stderr, flush=True)
+        t_leg = time.perf_counter()
+
     if args.fp64_steps > 0 and args.precision == "fp32":
         line["fp64"] = fp64_leg(P, torch, m, args.fp64_steps, algorithmic_flops_per_rhs(m))
+        leg_done("fp64")
     if args.spectrum:
         line.update(spectrum_legs(P, torch, w, m, params, grid, args))
+        leg_done("spectrum")
     del s
     if args.multi:
         line["multi_instance"] = multi_instance(P, torch, args.precision, stream.cuda_stream,
                                                 compare=args.multi > 1)
+        leg_done("multi-instance")
     if args.grad:
         line["gradient"] = gradient_timing(P, torch, stream.cuda_stream)
+        leg_done("gradient")
     if args.cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(params)
+        leg_done("cpu baseline")
     print(json.dumps(line))
 
 

@@ -96,7 +96,7 @@ def test_batch_propagate_matches_single_model_path(instances):
 
 def test_batch_response_parity(instances):
     ps, os_ = instances
-    grid = {"n1": 4, "n3": 4, "steps_per_sample": 5, "t2_steps": [0, 6]}
+    grid = {"n1": 3, "n3": 3, "steps_per_sample": 4, "t2_steps": [0, 5]}
     models = [P.heom_model_build(p) for p in ps]
     rhos, refs = [], []
     for m, o in zip(models, os_):

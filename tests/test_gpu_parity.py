@@ -417,11 +417,17 @@ def test_full_size_fp32_spectrum_matches_fp64():
 
 @pytest.mark.parametrize("which,depth", [("cfg1", None), ("cfg2", 2)])
 def test_krylov_equilibration_reaches_stationary_state(which, depth):
+    # the oracle's sparse direct solve; for the two-mode model (17,500
+    # unknowns, minutes of CPU) it is stored by tests/golden/make_stationary.py
     params = _params(which, depth)
     if which == "cfg1":
         params["dt"] = 0.05
-    o = om.build(params)
-    ref = oh.stationary_state(o)
+        ref = oh.stationary_state(om.build(params))
+    else:
+        import os
+        z = np.load(os.path.join(os.path.dirname(__file__), "golden", "cfg2_depth2_rho_eq.npz"))
+        assert int(z["depth"]) == depth
+        ref = z["rho"]
     m = P.heom_model_build(params)
     rho, applies, res = P.heom_equilibrate_krylov(m, tol=1e-11)
     assert res <= 1e-11 and applies > 0
