@@ -36,7 +36,10 @@ sys.path.insert(0, ROOT)
 # scaled by the counters' readings for kernels of known size.  Keyed by the
 # kernel source hash: a changed kernel reports traffic null until re-profiled.
 PROFILED_TRAFFIC = {  # source hash -> kernel choice -> bytes per launch
-    "1e73106a80d7a912": {  # FP32 at this shape: both choices run the runtime-shape kernel
+    # 7ede351588b593dc: profiled as 1e73106a80d7a912; the later edits touch the multi-instance
+    # and single-launch kernels only (the benchmark kernel's device assembly,
+    # hipcc --cuda-device-only -S, is instruction for instruction the same)
+    "7ede351588b593dc": {  # FP32 at this shape: both choices run the runtime-shape kernel
         "mfma": {"read_GB": 319.4, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
         "mfma_dyn": {"read_GB": 319.4, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
         # the FP64 leg: 32 trajectories
@@ -124,8 +127,13 @@ def batch_forms(P, torch, b, models, precision, n_traj=8, steps=5):
         s.set_ground()
         states.append(s)
     chosen, tune_ms = P.heom_batch_autotune(b, precision, n_traj=n_traj, reps=3)
+    shapes = {}
+    for nb in sorted({(m.d + 15) // 16 for m in models}):
+        wg, lds = P.heom_batch_get_class_shape(b, nb)
+        shapes[f"d<={16 * nb}"] = {"workgroups_per_cu": wg,
+                                   "neighbour_sums": {1: "lds", 0: "registers", -1: "default"}[lds]}
     out = {"trajectories_per_instance": n_traj, "steps": steps, "autotune_choice": chosen,
-           "autotune_ms_per_step": tune_ms}
+           "autotune_ms_per_step": tune_ms, "class_shapes": shapes}
     items = n_traj * sum(m.n_ado for m in models)
     for form, graph in (("per_class", 0), ("single", 0), (chosen, steps)):
         P.heom_batch_set_launch(b, form)

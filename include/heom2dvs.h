@@ -434,14 +434,26 @@ int heom_batch_get_launch(const heom_batch* batch, int* launch_out);
  * if capture fails the batch falls back to direct launches. */
 int heom_batch_set_graph_steps(heom_batch* batch, int steps);
 /* Measure the launch forms on scratch states of n_traj trajectories per
- * instance (ground state, precision HEOM_FP32 or HEOM_FP64): the time per
- * matrix of each size class alone (kept as the single launch's work
- * weights), then `reps` RK4 steps per class launches and, where allowed,
- * as single launches; HEOM_BATCH_AUTO then resolves to the faster.
+ * instance (ground state, precision HEOM_FP32 or HEOM_FP64): each size class
+ * alone in its launch shapes (heom_batch_get_class_shape; the fastest is
+ * kept, and the LDS form's time per matrix per workgroup becomes the single
+ * launch's work weight), then `reps` RK4 steps per class launches and, where
+ * allowed, as single launches; HEOM_BATCH_AUTO then resolves to the faster.
  * ms_out (may be null): [per-class, single] milliseconds per RK4 step (NaN
  * when the single form is not allowed).  Allocates 3 x n_traj hierarchies per
  * instance for the duration of the call. */
 int heom_batch_autotune(heom_batch* batch, int precision, int n_traj, int reps, double* ms_out);
+/* Launch shape heom_batch_autotune chose for the per-class launch of size
+ * class nb = ceil(d/16) (1..7): resident workgroups per CU (0: as many as LDS
+ * and registers allow) and the neighbour-sum form (1: accumulated in LDS,
+ * 0: in registers, -1: the class's only / default form).  The tuner times,
+ * per class alone, the most and half the workgroups per CU with both forms
+ * where both exist, and keeps the fastest. */
+int heom_batch_get_class_shape(const heom_batch* batch, int nb, int* wg_per_cu, int* lds_sums);
+/* Set that shape by hand (same meanings; lds_sums 0 or 1 only for the FP32
+ * classes nb <= 4, which have both forms; FP64 batches always use the LDS
+ * form).  HEOM_ERR_PARAM for values outside these ranges. */
+int heom_batch_set_class_shape(heom_batch* batch, int nb, int wg_per_cu, int lds_sums);
 
 /* ------------------------------------------------------ kernel choice -- */
 /* Implementations of the fused RHS / RK4-stage kernel:

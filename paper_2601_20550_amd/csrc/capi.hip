@@ -882,6 +882,7 @@ struct heom_batch {
   int launch = HEOM_BATCH_AUTO;   // requested launch form
   int tuned = 0;                  // form chosen by heom_batch_autotune (0: none yet)
   double class_cost[8] = {};      // measured time per matrix of each size class (0: cost model)
+  heom::MultiShape class_shape[8];  // per-class launch shape (autotuned; defaults otherwise)
   int graph_steps = 0;            // RK4 steps per captured graph (0: direct launches)
   hipStream_t cap_stream = nullptr;
   ~heom_batch() {
@@ -911,6 +912,7 @@ struct BatchProp {
   struct Class {
     int nb = 0, vw = 1, n_inst = 0;
     long long n_items = 0;
+    heom::MultiShape shape;
     DevBuf desc[2][4];
   };
   std::vector<Class> classes;
@@ -954,6 +956,7 @@ struct BatchProp {
     for (auto& kv : by_nb) {
       Class c;
       c.nb = kv.first;
+      c.shape = b->class_shape[c.nb];
       c.n_inst = static_cast<int>(kv.second.size());
       const int full_vw = 16 / static_cast<int>(sizeof(T));
       c.vw = full_vw;
@@ -1035,7 +1038,7 @@ struct BatchProp {
     }
     for (auto& c : classes)
       heom::launch_rhs_mfma_multi<T>(c.desc[a][st].template as<heom::InstDesc<T>>(), c.n_inst, c.nb, c.vw, coef,
-                                     c.n_items, stream);
+                                     c.n_items, stream, c.shape);
   }
 
   void direct_steps(heom_batch* b, int n_steps, bool adjoint, hipStream_t stream) {
@@ -1132,17 +1135,41 @@ void batch_autotune(heom_batch* b, int n_traj, int reps, double* ms_out) {
   std::vector<int> nbs;
   for (auto& c : pc.classes) {
     nbs.push_back(c.nb);
-    hip_check(hipEventRecord(guard.e0, b->stream), "event record");
-    for (int k = 0; k < reps; ++k)
-      for (int s4 = 0; s4 < 4; ++s4)
-        heom::launch_rhs_mfma_multi<T>(c.desc[0][s4].template as<heom::InstDesc<T>>(), c.n_inst, c.nb, c.vw,
-                                       coef[s4], c.n_items, b->stream);
-    hip_check(hipEventRecord(guard.e1, b->stream), "event record");
-    // time per matrix per workgroup: what sets how many of the single
-    // launch's workgroups the class needs to finish with the others
-    const double grid_c = static_cast<double>(heom::rhs_mfma_multi_grid<T>(c.nb, c.vw, c.n_items));
-    b->class_cost[c.nb] =
-        elapsed() * grid_c / (4.0 * reps * static_cast<double>(std::max<long long>(1, c.n_items)));
+    // launch shapes of the class alone: the most and half the resident
+    // workgroups per CU, each with both neighbour-sum forms where both exist
+    const int max_wg = static_cast<int>(std::max<long long>(
+        1, heom::rhs_mfma_multi_grid<T>(c.nb, c.vw, 1LL << 40, heom::MultiShape()) / heom::cu_count()));
+    std::vector<int> wgs = {max_wg};
+    if (max_wg / 2 >= 1) wgs.push_back(max_wg / 2);
+    const std::vector<int> xls = heom::multi_has_alt_xl<T>(c.nb) ? std::vector<int>{0, 1} : std::vector<int>{-1};
+    std::vector<heom::MultiShape> cand;
+    for (int wg : wgs)
+      for (int xl : xls) cand.push_back(heom::MultiShape{wg, xl});
+    double best_ms = 0.0;
+    heom::MultiShape best;
+    for (const auto& sh : cand) {
+      hip_check(hipEventRecord(guard.e0, b->stream), "event record");
+      for (int k = 0; k < reps; ++k)
+        for (int s4 = 0; s4 < 4; ++s4)
+          heom::launch_rhs_mfma_multi<T>(c.desc[0][s4].template as<heom::InstDesc<T>>(), c.n_inst, c.nb, c.vw,
+                                         coef[s4], c.n_items, b->stream, sh);
+      hip_check(hipEventRecord(guard.e1, b->stream), "event record");
+      const double ms = elapsed();
+      if (best_ms == 0.0 || ms < best_ms) {
+        best_ms = ms;
+        best = sh;
+      }
+      // time per matrix per workgroup of the LDS neighbour-sum form at the
+      // most workgroups (the form the single launch runs): what sets how many
+      // of the single launch's workgroups the class needs
+      if (sh.wg_per_cu == max_wg && (sh.xl == 1 || (sh.xl < 0))) {
+        const double grid_c = static_cast<double>(heom::rhs_mfma_multi_grid<T>(c.nb, c.vw, c.n_items, sh));
+        b->class_cost[c.nb] =
+            ms * grid_c / (4.0 * reps * static_cast<double>(std::max<long long>(1, c.n_items)));
+      }
+    }
+    b->class_shape[c.nb] = best;
+    c.shape = best;
   }
   hip_check(hipEventRecord(guard.e0, b->stream), "event record");
   pc.direct_steps(b, reps, false, b->stream);
@@ -2676,6 +2703,7 @@ int heom_batch_response_2d(heom_batch* b, const heom_state* const* rho_eq, const
       sub.launch = b->launch;
       sub.tuned = b->tuned;
       std::copy(std::begin(b->class_cost), std::end(b->class_cost), std::begin(sub.class_cost));
+      std::copy(std::begin(b->class_shape), std::end(b->class_shape), std::begin(sub.class_shape));
       sub.graph_steps = b->graph_steps;
       if (precision == HEOM_FP64)
         batch_response_adjoint<double>(&sub, rho_eq + i0, g, R_out + i0);
@@ -2702,6 +2730,24 @@ int heom_batch_get_launch(const heom_batch* b, int* out) {
   return guarded([&] {
     if (!b || !out) throw HeomError(HEOM_ERR_PARAM, "null argument");
     *out = b->resolved_launch();
+  });
+}
+
+int heom_batch_set_class_shape(heom_batch* b, int nb, int wg_per_cu, int lds_sums) {
+  return guarded([&] {
+    if (!b || nb < 1 || nb > 7 || wg_per_cu < 0 || lds_sums < -1 || lds_sums > 1)
+      throw HeomError(HEOM_ERR_PARAM, "bad arguments");
+    if (lds_sums >= 0 && !heom::multi_has_alt_xl<float>(nb))
+      throw HeomError(HEOM_ERR_PARAM, "this size class has one neighbour-sum form only");
+    b->class_shape[nb] = heom::MultiShape{wg_per_cu, lds_sums};
+  });
+}
+
+int heom_batch_get_class_shape(const heom_batch* b, int nb, int* wg_per_cu, int* lds_sums) {
+  return guarded([&] {
+    if (!b || !wg_per_cu || !lds_sums || nb < 1 || nb > 7) throw HeomError(HEOM_ERR_PARAM, "bad arguments");
+    *wg_per_cu = b->class_shape[nb].wg_per_cu;
+    *lds_sums = b->class_shape[nb].xl;
   });
 }
 

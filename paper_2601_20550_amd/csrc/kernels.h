@@ -100,12 +100,22 @@ struct InstDesc {
 // (nb = ceil(d/16) equal for all) in one persistent launch.  desc: device
 // array of n_inst descriptors sorted by item_begin; vw = 16 / sizeof(T) if
 // every instance has d divisible by it, else 1.
+// Launch shape of one class (0 / -1: the defaults): resident workgroups per
+// CU (at most what LDS and registers allow) and the neighbour-sum form
+// (1: X_s accumulated in LDS, 0: in registers; only where both exist).
+struct MultiShape {
+  int wg_per_cu = 0;
+  int xl = -1;
+};
 template <typename T>
 void launch_rhs_mfma_multi(const InstDesc<T>* desc, int n_inst, int nb, int vw, double coef, long long n_items,
-                           hipStream_t stream);
+                           hipStream_t stream, MultiShape shape = MultiShape());
 // Workgroups that launch uses for one class.
 template <typename T>
-long long rhs_mfma_multi_grid(int nb, int vw, long long n_items);
+long long rhs_mfma_multi_grid(int nb, int vw, long long n_items, MultiShape shape = MultiShape());
+// Whether both neighbour-sum forms exist for this class.
+template <typename T>
+bool multi_has_alt_xl(int nb);
 
 // One size class of a single-launch multi-class stage: its instances are
 // desc[inst_first, inst_first + n_inst) (items numbered from 0 within the

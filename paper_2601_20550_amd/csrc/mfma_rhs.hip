@@ -176,10 +176,10 @@ constexpr bool x_in_lds() {
   return sizeof(T) == 8 || NB == 5;
 }
 // minimum waves per SIMD requested from the register allocator
-template <typename T, int NB>
+template <typename T, int NB, bool XL = x_in_lds<T, NB>()>
 constexpr int minw_of() {
   if (wpr_of<T, NB>() == 2) return 3;
-  if (sizeof(T) == 4) return x_in_lds<T, NB>() ? 4 : 2;
+  if (sizeof(T) == 4) return XL ? 4 : 2;
   return 1;
 }
 
@@ -683,7 +683,7 @@ __global__ __launch_bounds__((NB * 64 * wpr_of<T, NB>()), MINW) void rhs_mfma_ke
 // persistent launch.  Instance i owns items [desc[i].item_begin,
 // desc[i+1].item_begin).  A workgroup re-stages H and v_s whenever the
 // instance of its next item differs from the previous one.
-template <typename T, int NB, int MINW, int VW>
+template <typename T, int NB, int MINW, int VW, bool XL>
 __global__ __launch_bounds__((NB * 64 * wpr_of<T, NB>()), MINW) void rhs_mfma_multi_kernel(const InstDesc<T>* __restrict__ desc,
                                                                        int n_inst, T coef, long long n_items) {
   using L = Lds<T, NB>;
@@ -707,8 +707,8 @@ __global__ __launch_bounds__((NB * 64 * wpr_of<T, NB>()), MINW) void rhs_mfma_mu
       stage_operators<T, NB, DynShape>(di.op, sh, di.Hp, sRe, sH, sV);
       cur = lo;
     }
-    rhs_item<T, NB, DynShape, VW, wpr_of<T, NB>()>(di.op, sh, di.in, di.y, di.out, coef, item - di.item_begin, sRe,
-                                                  sIm, sH, sV);
+    rhs_item<T, NB, DynShape, VW, wpr_of<T, NB>(), XL>(di.op, sh, di.in, di.y, di.out, coef, item - di.item_begin,
+                                                      sRe, sIm, sH, sV);
   }
 }
 
@@ -896,12 +896,13 @@ void launch_rhs_mfma(const DevOps<T>& op, const T* Hp, const T* in, const T* y, 
 
 namespace {
 
-// persistent grid of the per-class launch
-template <typename T, int NB, int VW>
-long long multi_grid_nb(long long n_items) {
+// persistent grid of the per-class launch: the CU count times the
+// workgroups per CU that LDS and registers allow (at most 8), or fewer when
+// the shape asks for it
+template <typename T, int NB, int VW, bool XL>
+long long multi_grid_nb(long long n_items, int wg_per_cu) {
   const size_t lds = Lds<T, NB>::bytes;
-  constexpr int MINW = minw_of<T, NB>();
-  auto kern = &rhs_mfma_multi_kernel<T, NB, MINW, VW>;
+  auto kern = &rhs_mfma_multi_kernel<T, NB, minw_of<T, NB, XL>(), VW, XL>;
   static bool configured = false;
   if (!configured) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -916,60 +917,109 @@ long long multi_grid_nb(long long n_items) {
                                                    NB * 64 * wpr_of<T, NB>(), lds) == hipSuccess &&
       fit > 0 && fit < wg)
     wg = fit;
+  if (wg_per_cu > 0 && wg_per_cu < wg) wg = wg_per_cu;
   long long grid = static_cast<long long>(cu_count()) * wg;
   if (grid > n_items) grid = n_items;
   return grid;
 }
 
-template <typename T, int NB, int VW>
-void launch_multi_nb(const InstDesc<T>* desc, int n_inst, T coef, long long n_items, hipStream_t stream) {
+template <typename T, int NB, int VW, bool XL>
+void launch_multi_nb(const InstDesc<T>* desc, int n_inst, T coef, long long n_items, int wg_per_cu,
+                     hipStream_t stream) {
   const size_t lds = Lds<T, NB>::bytes;
-  constexpr int MINW = minw_of<T, NB>();
-  auto kern = &rhs_mfma_multi_kernel<T, NB, MINW, VW>;
-  const long long grid = multi_grid_nb<T, NB, VW>(n_items);
+  auto kern = &rhs_mfma_multi_kernel<T, NB, minw_of<T, NB, XL>(), VW, XL>;
+  const long long grid = multi_grid_nb<T, NB, VW, XL>(n_items, wg_per_cu);
   hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(NB * 64 * wpr_of<T, NB>()), lds, stream, desc,
-                     n_inst, coef,
-                     n_items);
+                     n_inst, coef, n_items);
+}
+
+// the alternative neighbour-sum form exists for the FP32 classes whose
+// default keeps X_s in registers and whose LDS form the single-launch kernel
+// also runs (ceil(d/16) <= 4)
+template <typename T, int NB>
+constexpr bool has_alt_xl() {
+  return sizeof(T) == 4 && NB <= 4;
 }
 
 template <typename T, int NB>
-void launch_multi_vw(const InstDesc<T>* desc, int n_inst, int vw, T coef, long long n_items, hipStream_t stream) {
-  if (vw == 16 / static_cast<int>(sizeof(T)))
-    launch_multi_nb<T, NB, 16 / sizeof(T)>(desc, n_inst, coef, n_items, stream);
-  else
-    launch_multi_nb<T, NB, 1>(desc, n_inst, coef, n_items, stream);
+bool use_xl(int xl) {
+  if constexpr (has_alt_xl<T, NB>()) {
+    return xl < 0 ? x_in_lds<T, NB>() : xl != 0;
+  } else {
+    return x_in_lds<T, NB>();
+  }
+}
+
+template <typename T, int NB>
+void launch_multi_vw(const InstDesc<T>* desc, int n_inst, int vw, T coef, long long n_items, MultiShape shape,
+                     hipStream_t stream) {
+  constexpr int VF = 16 / sizeof(T);
+  constexpr bool DEF = x_in_lds<T, NB>();
+  if (has_alt_xl<T, NB>() && use_xl<T, NB>(shape.xl) != DEF) {
+    if constexpr (has_alt_xl<T, NB>()) {
+      if (vw == VF) launch_multi_nb<T, NB, VF, !DEF>(desc, n_inst, coef, n_items, shape.wg_per_cu, stream);
+      else launch_multi_nb<T, NB, 1, !DEF>(desc, n_inst, coef, n_items, shape.wg_per_cu, stream);
+    }
+    return;
+  }
+  if (vw == VF) launch_multi_nb<T, NB, VF, DEF>(desc, n_inst, coef, n_items, shape.wg_per_cu, stream);
+  else launch_multi_nb<T, NB, 1, DEF>(desc, n_inst, coef, n_items, shape.wg_per_cu, stream);
+}
+
+template <typename T, int NB>
+long long multi_grid_vw(int vw, long long n_items, MultiShape shape) {
+  constexpr int VF = 16 / sizeof(T);
+  constexpr bool DEF = x_in_lds<T, NB>();
+  if (has_alt_xl<T, NB>() && use_xl<T, NB>(shape.xl) != DEF) {
+    if constexpr (has_alt_xl<T, NB>()) {
+      return vw == VF ? multi_grid_nb<T, NB, VF, !DEF>(n_items, shape.wg_per_cu)
+                      : multi_grid_nb<T, NB, 1, !DEF>(n_items, shape.wg_per_cu);
+    }
+  }
+  return vw == VF ? multi_grid_nb<T, NB, VF, DEF>(n_items, shape.wg_per_cu)
+                  : multi_grid_nb<T, NB, 1, DEF>(n_items, shape.wg_per_cu);
 }
 
 }  // namespace
 
 template <typename T>
-long long rhs_mfma_multi_grid(int nb, int vw, long long n_items) {
-  const bool full = vw == 16 / static_cast<int>(sizeof(T));
+bool multi_has_alt_xl(int nb) {
   switch (nb) {
-    case 1: return full ? multi_grid_nb<T, 1, 16 / sizeof(T)>(n_items) : multi_grid_nb<T, 1, 1>(n_items);
-    case 2: return full ? multi_grid_nb<T, 2, 16 / sizeof(T)>(n_items) : multi_grid_nb<T, 2, 1>(n_items);
-    case 3: return full ? multi_grid_nb<T, 3, 16 / sizeof(T)>(n_items) : multi_grid_nb<T, 3, 1>(n_items);
-    case 4: return full ? multi_grid_nb<T, 4, 16 / sizeof(T)>(n_items) : multi_grid_nb<T, 4, 1>(n_items);
-    case 5: return full ? multi_grid_nb<T, 5, 16 / sizeof(T)>(n_items) : multi_grid_nb<T, 5, 1>(n_items);
-    case 6: return full ? multi_grid_nb<T, 6, 16 / sizeof(T)>(n_items) : multi_grid_nb<T, 6, 1>(n_items);
-    case 7: return full ? multi_grid_nb<T, 7, 16 / sizeof(T)>(n_items) : multi_grid_nb<T, 7, 1>(n_items);
+    case 1: return has_alt_xl<T, 1>();
+    case 2: return has_alt_xl<T, 2>();
+    case 3: return has_alt_xl<T, 3>();
+    case 4: return has_alt_xl<T, 4>();
+    default: return false;
+  }
+}
+
+template <typename T>
+long long rhs_mfma_multi_grid(int nb, int vw, long long n_items, MultiShape shape) {
+  switch (nb) {
+    case 1: return multi_grid_vw<T, 1>(vw, n_items, shape);
+    case 2: return multi_grid_vw<T, 2>(vw, n_items, shape);
+    case 3: return multi_grid_vw<T, 3>(vw, n_items, shape);
+    case 4: return multi_grid_vw<T, 4>(vw, n_items, shape);
+    case 5: return multi_grid_vw<T, 5>(vw, n_items, shape);
+    case 6: return multi_grid_vw<T, 6>(vw, n_items, shape);
+    case 7: return multi_grid_vw<T, 7>(vw, n_items, shape);
     default: throw std::runtime_error("multi-instance MFMA kernel supports ceil(d/16) <= 7");
   }
 }
 
 template <typename T>
 void launch_rhs_mfma_multi(const InstDesc<T>* desc, int n_inst, int nb, int vw, double coef, long long n_items,
-                           hipStream_t stream) {
+                           hipStream_t stream, MultiShape shape) {
   if (n_items == 0 || n_inst == 0) return;
   const T c = static_cast<T>(coef);
   switch (nb) {
-    case 1: launch_multi_vw<T, 1>(desc, n_inst, vw, c, n_items, stream); break;
-    case 2: launch_multi_vw<T, 2>(desc, n_inst, vw, c, n_items, stream); break;
-    case 3: launch_multi_vw<T, 3>(desc, n_inst, vw, c, n_items, stream); break;
-    case 4: launch_multi_vw<T, 4>(desc, n_inst, vw, c, n_items, stream); break;
-    case 5: launch_multi_vw<T, 5>(desc, n_inst, vw, c, n_items, stream); break;
-    case 6: launch_multi_vw<T, 6>(desc, n_inst, vw, c, n_items, stream); break;
-    case 7: launch_multi_vw<T, 7>(desc, n_inst, vw, c, n_items, stream); break;
+    case 1: launch_multi_vw<T, 1>(desc, n_inst, vw, c, n_items, shape, stream); break;
+    case 2: launch_multi_vw<T, 2>(desc, n_inst, vw, c, n_items, shape, stream); break;
+    case 3: launch_multi_vw<T, 3>(desc, n_inst, vw, c, n_items, shape, stream); break;
+    case 4: launch_multi_vw<T, 4>(desc, n_inst, vw, c, n_items, shape, stream); break;
+    case 5: launch_multi_vw<T, 5>(desc, n_inst, vw, c, n_items, shape, stream); break;
+    case 6: launch_multi_vw<T, 6>(desc, n_inst, vw, c, n_items, shape, stream); break;
+    case 7: launch_multi_vw<T, 7>(desc, n_inst, vw, c, n_items, shape, stream); break;
     default: throw std::runtime_error("multi-instance MFMA kernel supports ceil(d/16) <= 7");
   }
   hipError_t e = hipGetLastError();
@@ -1068,10 +1118,14 @@ template void launch_rhs_mfma_fused<float>(const FusedClass*, int, const InstDes
 template void launch_rhs_mfma_fused<double>(const FusedClass*, int, const InstDesc<double>*, int, size_t, int,
                                             double, hipStream_t);
 
-template long long rhs_mfma_multi_grid<float>(int, int, long long);
-template long long rhs_mfma_multi_grid<double>(int, int, long long);
-template void launch_rhs_mfma_multi<float>(const InstDesc<float>*, int, int, int, double, long long, hipStream_t);
-template void launch_rhs_mfma_multi<double>(const InstDesc<double>*, int, int, int, double, long long, hipStream_t);
+template bool multi_has_alt_xl<float>(int);
+template bool multi_has_alt_xl<double>(int);
+template long long rhs_mfma_multi_grid<float>(int, int, long long, MultiShape);
+template long long rhs_mfma_multi_grid<double>(int, int, long long, MultiShape);
+template void launch_rhs_mfma_multi<float>(const InstDesc<float>*, int, int, int, double, long long, hipStream_t,
+                                           MultiShape);
+template void launch_rhs_mfma_multi<double>(const InstDesc<double>*, int, int, int, double, long long, hipStream_t,
+                                            MultiShape);
 
 template bool mfma_static_shape<float>(const DevOps<float>&);
 template bool mfma_static_shape<double>(const DevOps<double>&);

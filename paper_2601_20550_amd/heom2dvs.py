@@ -145,6 +145,8 @@ _SIGS = {
     "heom_batch_get_launch": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
     "heom_batch_set_graph_steps": (C.c_int, [C.c_void_p, C.c_int]),
     "heom_batch_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p]),
+    "heom_batch_get_class_shape": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "heom_batch_set_class_shape": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
     "heom_model_set_kernel": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "heom_model_set_graph_steps": (C.c_int, [C.c_void_p, C.c_int]),
     "heom_model_set_progress": (C.c_int, [C.c_void_p, _PROGRESS_FN, C.c_void_p, C.c_int]),
@@ -694,6 +696,17 @@ def heom_batch_get_launch(batch: Batch) -> str:
     out = C.c_int()
     _check(_lib.heom_batch_get_launch(batch.handle, C.byref(out)))
     return {v: k for k, v in BATCH_LAUNCH.items()}[out.value]
+
+
+def heom_batch_get_class_shape(batch: Batch, nb: int):
+    """(workgroups per CU, neighbour-sum form) of size class nb's launch."""
+    wg, xl = C.c_int(), C.c_int()
+    _check(_lib.heom_batch_get_class_shape(batch.handle, int(nb), C.byref(wg), C.byref(xl)))
+    return wg.value, xl.value
+
+
+def heom_batch_set_class_shape(batch: Batch, nb: int, wg_per_cu=0, lds_sums=-1):
+    _check(_lib.heom_batch_set_class_shape(batch.handle, int(nb), int(wg_per_cu), int(lds_sums)))
 
 
 def heom_batch_set_graph_steps(batch: Batch, steps: int):

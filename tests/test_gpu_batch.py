@@ -285,6 +285,9 @@ def test_batch_autotune_picks_the_faster_form(instances):
     assert np.isfinite(ms["per_class"]) and np.isfinite(ms["single"])
     assert chosen == ("single" if ms["single"] < ms["per_class"] else "per_class")
     assert P.heom_batch_get_launch(b) == chosen
+    for nb in (1, 2, 5):  # the classes of these instances: a tuned shape each
+        wg, lds = P.heom_batch_get_class_shape(b, nb)
+        assert wg >= 1 and lds in ((0, 1) if nb <= 4 else (-1,))
     xs, st = _random_states(models, os_, "fp32", 140)
     P.heom_batch_propagate(b, st, 2)
     for o, x, s in zip(os_, xs, st):
@@ -303,3 +306,26 @@ def test_batch_autotune_picks_the_faster_form(instances):
     assert e.value.code == P.heom2dvs.HEOM_ERR_PARAM
     chosen, ms = P.heom_batch_autotune(bw, "fp32", n_traj=1, reps=1)
     assert chosen == "per_class" and np.isnan(ms["single"])
+
+
+@pytest.mark.parametrize("wg,lds", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_per_class_launch_shapes_parity(wg, lds):
+    # the per-class launch with either neighbour-sum form (registers / LDS)
+    # and with one workgroup per CU, for the FP32 classes that have both forms
+    # (d = 6, 25, 48, 64) and the d = 80 class, against the oracle
+    ps = _class_instances(True)
+    os_ = [om.build(p) for p in ps]
+    models = [P.heom_model_build(p) for p in ps]
+    xs, st = _random_states(models, os_, "fp32", 160)
+    b = P.heom_batch_create(models)
+    for nb in (1, 2, 3, 4):
+        P.heom_batch_set_class_shape(b, nb, wg, lds)
+        assert P.heom_batch_get_class_shape(b, nb) == (wg, lds)
+    P.heom_batch_set_class_shape(b, 5, wg, -1)
+    with pytest.raises(P.heom2dvs.HeomError) as e:
+        P.heom_batch_set_class_shape(b, 5, 0, 1)
+    assert e.value.code == P.heom2dvs.HEOM_ERR_PARAM
+    P.heom_batch_propagate(b, st, 2)
+    for i, (o, x, s) in enumerate(zip(os_, xs, st)):
+        ref = np.stack([oh.propagate(o, x[t], 2) for t in range(x.shape[0])])
+        assert _relerr(s.download(), ref) < 1e-5, (i, o.d)
