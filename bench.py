@@ -376,7 +376,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path shards into independent "
-              "trajectory batches (see DESIGN.md); run with --gpus 1", file=sys.stderr)
+              "trajectory batches; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
