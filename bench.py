@@ -36,10 +36,11 @@ sys.path.insert(0, ROOT)
 # scaled by the counters' readings for kernels of known size.  Keyed by the
 # kernel source hash: a changed kernel reports traffic null until re-profiled.
 PROFILED_TRAFFIC = {  # source hash -> kernel choice -> bytes per launch
-    # 7ede351588b593dc: profiled as 1e73106a80d7a912; the later edits touch the multi-instance
-    # and single-launch kernels only (the benchmark kernel's device assembly,
-    # hipcc --cuda-device-only -S, is instruction for instruction the same)
-    "7ede351588b593dc": {  # FP32 at this shape: both choices run the runtime-shape kernel
+    # db1af44dac001634: profiled as 1e73106a80d7a912; the later edits add the
+    # multi-instance, single-launch and H-from-global kernels only (the device
+    # assembly of every rhs_mfma_kernel instantiation, hipcc --cuda-device-only -S,
+    # is instruction for instruction the same)
+    "db1af44dac001634": {  # FP32 at this shape: both choices run the runtime-shape kernel
         "mfma": {"read_GB": 319.4, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
         "mfma_dyn": {"read_GB": 319.4, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
         # the FP64 leg: 32 trajectories
@@ -73,7 +74,8 @@ def algorithmic_flops_per_rhs(model):
 
 
 KERNEL_FILES = {"generic": ("kernels.hip", "rhs_generic_kernel"), "mfma": ("mfma_rhs.hip", "rhs_mfma_kernel"),
-                "mfma_dyn": ("mfma_rhs.hip", "rhs_mfma_kernel"), "kron": ("kron_rhs.hip", "rhs_kron_kernel")}
+                "mfma_dyn": ("mfma_rhs.hip", "rhs_mfma_kernel"), "kron": ("kron_rhs.hip", "rhs_kron_kernel"),
+                "mfma_gh": ("mfma_rhs.hip", "rhs_mfma_gh_kernel")}
 
 
 def kernel_source_hash(kernel="mfma"):
@@ -372,7 +374,7 @@ def main():
                          "scale, 3 x 4 levels, K = 4 Pade, depth 5 (15,504 ADOs), 300 K assumed; "
                          "brownian: cfg3's modes with Brownian baths (complex rate pairs), "
                          "12 terms, depth 5 (6188 ADOs)")
-    ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "mfma", "mfma_dyn", "kron"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "mfma", "mfma_dyn", "kron", "mfma_gh"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path shards into independent "

@@ -479,6 +479,14 @@ int heom_batch_set_class_shape(heom_batch* batch, int nb, int wg_per_cu, int lds
  *                         reordering is invisible at this interface.
  * (measured slower than HEOM_KERNEL_MFMA on MI355X at the three-mode depth-6
  * benchmark shape, so it is not the default; heom_autotune times it).
+ *   HEOM_KERNEL_MFMA_GH : FP32 matrix-core kernel for d in 65..80 (five
+ *                         16-row blocks) whose models keep at most 128
+ *                         single-mode operator values: HEOM_KERNEL_MFMA's
+ *                         algorithm with H read from its zero-padded global
+ *                         copy (L1 / L2 resident) instead of an LDS plane,
+ *                         so that three workgroups share a CU instead of two
+ *                         (measured slower than HEOM_KERNEL_MFMA at the
+ *                         three-mode depth-6 shape; heom_autotune times it).
  * Models start on HEOM_KERNEL_MFMA where it fits the LDS (FP32 d <= 112, FP64 d <= 80) and
  * every mode keeps at most 8 levels (the single-mode operators are staged in
  * 8 x 8 LDS slots), and on HEOM_KERNEL_GENERIC otherwise;
@@ -490,7 +498,8 @@ typedef enum {
   HEOM_KERNEL_GENERIC = 1,
   HEOM_KERNEL_MFMA = 2,
   HEOM_KERNEL_MFMA_DYN = 3,
-  HEOM_KERNEL_KRON = 4
+  HEOM_KERNEL_KRON = 4,
+  HEOM_KERNEL_MFMA_GH = 5
 } heom_kernel;
 int heom_model_set_kernel(heom_model* model, int precision, int kernel);
 int heom_model_get_kernel(const heom_model* model, int precision, int* kernel_out);
@@ -522,7 +531,7 @@ int heom_model_set_progress(heom_model* model, heom_progress_fn fn, void* ctx, i
  * run the same code are timed once) on a scratch batch of n_traj
  * trajectories in the given precision (one warm-up step, then reps RK4
  * steps each) and keeps the fastest for this model and precision.  ms_out
- * (may be NULL; HEOM_KERNEL_KRON + 1 entries) receives the measured time per
+ * (may be NULL; HEOM_KERNEL_MFMA_GH + 1 entries) receives the measured time per
  * RK4 step indexed by heom_kernel, NaN for variants not timed.  The
  * previous choice is kept when an error occurs. */
 int heom_autotune(heom_model* model, int n_traj, int precision, int reps, int* kernel_out,

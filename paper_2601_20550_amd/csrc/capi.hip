@@ -444,6 +444,8 @@ void launch_stage(heom_model* m, bool adjoint, const T* in, const T* y, T* out, 
   else if constexpr (std::is_same<T, float>::value) {
     if (k == HEOM_KERNEL_KRON)
       heom::launch_rhs_kron(m->kargs[adjoint ? 1 : 0], m->hm.d, in, y, out, coef, n_traj, m->stream);
+    else if (k == HEOM_KERNEL_MFMA_GH)
+      heom::launch_rhs_mfma_gh<T>(op, padded_H<T>(m), in, y, out, coef, n_traj, m->stream);
     else
       heom::launch_rhs_mfma<T>(op, padded_H<T>(m), in, y, out, coef, n_traj, k == HEOM_KERNEL_MFMA_DYN ? 1 : 0,
                                m->stream);
@@ -2778,7 +2780,7 @@ int heom_model_set_kernel(heom_model* m, int precision, int kernel) {
   return guarded([&] {
     require_device(m);
     if (precision != HEOM_FP64 && precision != HEOM_FP32) throw HeomError(HEOM_ERR_PARAM, "bad precision");
-    if (kernel < HEOM_KERNEL_AUTO || kernel > HEOM_KERNEL_KRON) throw HeomError(HEOM_ERR_PARAM, "bad kernel");
+    if (kernel < HEOM_KERNEL_AUTO || kernel > HEOM_KERNEL_MFMA_GH) throw HeomError(HEOM_ERR_PARAM, "bad kernel");
     const bool ok = precision == HEOM_FP64 ? heom::mfma_supported<double>(m->hm.d, m->hm.n_modes, m->hm.dims)
                                            : heom::mfma_supported<float>(m->hm.d, m->hm.n_modes, m->hm.dims);
     if (kernel == HEOM_KERNEL_AUTO) kernel = ok ? HEOM_KERNEL_MFMA : HEOM_KERNEL_GENERIC;
@@ -2786,6 +2788,10 @@ int heom_model_set_kernel(heom_model* m, int precision, int kernel) {
       throw HeomError(HEOM_ERR_PARAM, "the (S;4,4) matrix-core kernel needs FP32 and three modes of (4|5, 4, 4) levels");
     if ((kernel == HEOM_KERNEL_MFMA || kernel == HEOM_KERNEL_MFMA_DYN) && !ok)
       throw HeomError(HEOM_ERR_PARAM, "matrix-core kernel unsupported for this d");
+    if (kernel == HEOM_KERNEL_MFMA_GH &&
+        (precision != HEOM_FP32 || !heom::mfma_gh_supported<float>(m->hm.d, m->hm.n_modes, m->hm.dims)))
+      throw HeomError(HEOM_ERR_PARAM, "the H-from-global matrix-core kernel needs FP32, d in 65..80 and at most "
+                                      "128 single-mode operator values");
     m->kernel[precision] = kernel;
     m->clear_graphs();
   });
@@ -2848,8 +2854,10 @@ int heom_autotune(heom_model* m, int n_traj, int precision, int reps, int* kerne
     if (ok) cand.push_back(HEOM_KERNEL_MFMA);
     if (ok && distinct_dyn) cand.push_back(HEOM_KERNEL_MFMA_DYN);
     if (precision == HEOM_FP32 && m->kron) cand.push_back(HEOM_KERNEL_KRON);
+    if (precision == HEOM_FP32 && heom::mfma_gh_supported<float>(m->hm.d, m->hm.n_modes, m->hm.dims))
+      cand.push_back(HEOM_KERNEL_MFMA_GH);
     if (ms_out)
-      for (int k = 0; k <= HEOM_KERNEL_KRON; ++k) ms_out[k] = std::nan("");
+      for (int k = 0; k <= HEOM_KERNEL_MFMA_GH; ++k) ms_out[k] = std::nan("");
     int best = guard.kernel;
     double best_ms = 1e300;
     for (int k : cand) {

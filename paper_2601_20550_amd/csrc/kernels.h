@@ -45,6 +45,14 @@ bool mfma_supported(int d, int n_modes, const int* dims);
 template <typename T>
 void launch_rhs_mfma(const DevOps<T>& op, const T* Hp, const T* in, const T* y, T* out, double coef,
                      int n_traj, int variant, hipStream_t stream);
+// The matrix-core kernel with H read from its padded global copy instead of
+// LDS (three workgroups per CU): FP32, d in 65..80, packed v_s of at most
+// 128 values.  Hp as for launch_rhs_mfma.
+template <typename T>
+bool mfma_gh_supported(int d, int n_modes, const int* dims);
+template <typename T>
+void launch_rhs_mfma_gh(const DevOps<T>& op, const T* Hp, const T* in, const T* y, T* out, double coef, int n_traj,
+                        hipStream_t stream);
 // True when launch_rhs_mfma has a compile-time mode shape for this model
 // (otherwise variants 0 and 1 run the same kernel).
 template <typename T>

@@ -119,14 +119,20 @@ constexpr int lds_pad(size_t elem, int) { return elem == 4 ? 4 : 2; }
 
 // LDS layout (elements of T): rho planes Re, Im and H, each DP x LD with
 // LD = DP + lds_pad, then v_s (4 x 64 values).
-template <typename T, int NB>
+// With HG (H read from its zero-padded global copy instead of LDS) the H plane
+// is dropped and the single-mode operators are packed as in DevOps::v (at
+// most kPackedV values): 54.3 KB instead of 81.6 KB at d = 80 in FP32, so
+// three workgroups share a CU instead of two.
+constexpr int kPackedV = 128;
+
+template <typename T, int NB, bool HG = false>
 struct Lds {
   static constexpr int DP = 16 * NB;
   static constexpr int LD = DP + lds_pad(sizeof(T), NB);
   static constexpr int PLANE = DP * LD;
   static constexpr int HOFF = 2 * PLANE;
-  static constexpr int VOFF = HOFF + PLANE;
-  static constexpr size_t bytes = (VOFF + 4 * 64) * sizeof(T);
+  static constexpr int VOFF = HG ? HOFF : HOFF + PLANE;
+  static constexpr size_t bytes = (VOFF + (HG ? kPackedV : 4 * 64)) * sizeof(T);
 };
 
 // Vector of VW elements of T (one 16-byte global access per lane when
@@ -185,20 +191,22 @@ constexpr int minw_of() {
 
 // Stages H (zero padded to DP x DP), the single-mode operators v_s and zero
 // padding of the rho planes into LDS.
-template <typename T, int NB, typename Shape>
+template <typename T, int NB, typename Shape, bool HG = false>
 __device__ inline void stage_operators(const DevOps<T>& op, const Shape& sh, const T* __restrict__ Hp, T* sRe,
                                        T* sH, T* sV) {
-  using L = Lds<T, NB>;
+  using L = Lds<T, NB, HG>;
   constexpr int DP = L::DP, LD = L::LD, NT = NB * 64 * wpr_of<T, NB>();
-  for (int e = threadIdx.x; e < DP * DP; e += NT) {
-    const int r = e / DP, c = e - (e / DP) * DP;
-    sH[r * LD + c] = Hp[e];
+  if constexpr (!HG) {
+    for (int e = threadIdx.x; e < DP * DP; e += NT) {
+      const int r = e / DP, c = e - (e / DP) * DP;
+      sH[r * LD + c] = Hp[e];
+    }
   }
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     if (s >= sh.nm()) break;
     const int ds2 = sh.dim(s) * sh.dim(s);
-    for (int e = threadIdx.x; e < ds2; e += NT) sV[s * 64 + e] = op.v[op.v_off[s] + e];
+    for (int e = threadIdx.x; e < ds2; e += NT) sV[(HG ? op.v_off[s] : s * 64) + e] = op.v[op.v_off[s] + e];
   }
   // only the d x d block of the rho planes is rewritten per matrix
   for (int e = threadIdx.x; e < 2 * L::PLANE; e += NT) sRe[e] = T(0);
@@ -211,7 +219,7 @@ __device__ inline void stage_operators(const DevOps<T>& op, const Shape& sh, con
 // [ (w % WPR) JT, ... ) (JT = ceil(NB / WPR)); for the memory phases
 // (neighbour sums, epilogue) it owns the slab of 16 / WPR rows starting at
 // row (16 / WPR) w.
-template <typename T, int NB, typename Shape, int VW, int WPR, bool XL = x_in_lds<T, NB>()>
+template <typename T, int NB, typename Shape, int VW, int WPR, bool XL = x_in_lds<T, NB>(), bool HG = false>
 __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, const T* __restrict__ in,
                                          const T* y, T* out, T coef, long long item, T* sRe, T* sIm,
                                          const T* sH, const T* sV) {
@@ -220,6 +228,8 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
   using acc_t = typename M::acc;
   using vec_t = typename Vec<T, VW>::type;
   constexpr int DP = L::DP, LD = L::LD;
+  // row stride of H: the LDS plane, or the zero-padded DP x DP global copy
+  constexpr int HLD = HG ? DP : LD;
   constexpr int NT = NB * 64 * WPR;
   constexpr int JT = (NB + WPR - 1) / WPR;   // column tiles per wave
   constexpr int SR = 16 / WPR;               // slab rows per wave
@@ -287,13 +297,13 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
 #pragma unroll
     for (int blk = 0; blk < NB; ++blk) {
       const int kb = 16 * blk + 4 * lq;
-      const v4 hA4 = *reinterpret_cast<const v4*>(&sH[(rows0 + lr) * LD + kb]);
+      const v4 hA4 = *reinterpret_cast<const v4*>(&sH[(rows0 + lr) * HLD + kb]);
       const v4 aRe4 = *reinterpret_cast<const v4*>(&sRe[(rows0 + lr) * LD + kb]);
       const v4 aIm4 = *reinterpret_cast<const v4*>(&sIm[(rows0 + lr) * LD + kb]);
       v4 hB4[JT];
 #pragma unroll
       for (int jj = 0; jj < JT; ++jj)
-        if (j0 + jj < NB) hB4[jj] = *reinterpret_cast<const v4*>(&sH[(16 * (j0 + jj) + lr) * LD + kb]);
+        if (j0 + jj < NB) hB4[jj] = *reinterpret_cast<const v4*>(&sH[(16 * (j0 + jj) + lr) * HLD + kb]);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int k = kb + t;
@@ -315,7 +325,7 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
 #pragma unroll
     for (int kk = 0; kk < 4 * NB; ++kk) {
       const int k = 4 * kk + lq;
-      const T hA = sH[(rows0 + lr) * LD + k];
+      const T hA = sH[(rows0 + lr) * HLD + k];
       const T nhA = -hA;
       const T aRe = sRe[(rows0 + lr) * LD + k];
       const T naIm = -sIm[(rows0 + lr) * LD + k];
@@ -323,7 +333,7 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
       for (int jj = 0; jj < JT; ++jj) {
         if (j0 + jj < NB) {
           const int j = j0 + jj;
-          const T hB = sH[k * LD + 16 * j + lr];
+          const T hB = sH[k * HLD + 16 * j + lr];
           Rre[jj] = M::mma(hA, sIm[k * LD + 16 * j + lr], Rre[jj]);
           Rre[jj] = M::mma(naIm, hB, Rre[jj]);
           Rim[jj] = M::mma(nhA, sRe[k * LD + 16 * j + lr], Rim[jj]);
@@ -367,7 +377,7 @@ __device__ __forceinline__ void rhs_item(const DevOps<T>& op, const Shape& sh, c
     const int p1 = op.nb_ptr[n * op.n_modes + s + 1];
     if (p0 == p1) continue;  // uniform across the workgroup
     const int ds = sh.dim(s), st = sh.stride(s);
-    const T* vs = sV + s * 64;
+    const T* vs = sV + (HG ? op.v_off[s] : s * 64);
     bool have_w = false;
     if constexpr (XL) {
       __syncthreads();  // every wave is done with the previous LDS content
@@ -679,6 +689,27 @@ __global__ __launch_bounds__((NB * 64 * wpr_of<T, NB>()), MINW) void rhs_mfma_ke
     rhs_item<T, NB, Shape, VW, wpr_of<T, NB>()>(op, sh, in, y, out, coef, item, sRe, sIm, sH, sV);
 }
 
+// rhs_mfma_kernel with H read from its zero-padded global copy (L1 / L2
+// resident, 25.6 KB at d = 80 in FP32) and the v_s packed, for the LDS of
+// three workgroups per CU.
+template <typename T, int NB, typename Shape, int MINW, int VW>
+__global__ __launch_bounds__((NB * 64 * wpr_of<T, NB>()), MINW) void rhs_mfma_gh_kernel(DevOps<T> op,
+                                                                                       const T* __restrict__ Hp,
+                                                                                       const T* __restrict__ in,
+                                                                                       const T* y, T* out, T coef,
+                                                                                       long long n_items) {
+  using L = Lds<T, NB, true>;
+  extern __shared__ unsigned char smem_raw[];
+  T* sRe = reinterpret_cast<T*>(smem_raw);
+  T* sIm = sRe + L::PLANE;
+  T* sV = sRe + L::VOFF;
+  const Shape sh(op.dims, op.strides, op.n_modes, op.d);
+  stage_operators<T, NB, Shape, true>(op, sh, Hp, sRe, nullptr, sV);
+  for (long long item = blockIdx.x; item < n_items; item += gridDim.x)
+    rhs_item<T, NB, Shape, VW, wpr_of<T, NB>(), x_in_lds<T, NB>(), true>(op, sh, in, y, out, coef, item, sRe, sIm,
+                                                                         Hp, sV);
+}
+
 // Several model instances of one size class (same ceil(d/16)) in one
 // persistent launch.  Instance i owns items [desc[i].item_begin,
 // desc[i+1].item_begin).  A workgroup re-stages H and v_s whenever the
@@ -834,6 +865,59 @@ void launch_dyn(const DevOps<T>& op, const T* Hp, const T* in, const T* y, T* ou
 }
 
 }  // namespace
+
+namespace {
+
+template <typename T, int VW>
+void launch_gh_vw(const DevOps<T>& op, const T* Hp, const T* in, const T* y, T* out, T coef, long long n_items,
+                  hipStream_t stream) {
+  constexpr int NB = 5;
+  const size_t lds = Lds<T, NB, true>::bytes;
+  auto kern = &rhs_mfma_gh_kernel<T, NB, DynShape, minw_of<T, NB>(), VW>;
+  static bool configured = false;
+  if (!configured) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              static_cast<int>(lds));
+    configured = true;
+  }
+  int wg = static_cast<int>((160 * 1024) / lds);
+  int fit = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, reinterpret_cast<const void*>(kern),
+                                                   NB * 64 * wpr_of<T, NB>(), lds) == hipSuccess &&
+      fit > 0 && fit < wg)
+    wg = fit;
+  if (wg < 1) wg = 1;
+  long long grid = static_cast<long long>(cu_count()) * wg;
+  if (grid > n_items) grid = n_items;
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(NB * 64 * wpr_of<T, NB>()), lds, stream, op, Hp,
+                     in, y, out, coef, n_items);
+}
+
+}  // namespace
+
+template <typename T>
+bool mfma_gh_supported(int d, int n_modes, const int* dims) {
+  if (sizeof(T) != 4 || (d + 15) / 16 != 5 || !mfma_supported<T>(d, n_modes, dims)) return false;
+  int nv = 0;
+  for (int s = 0; s < n_modes; ++s) nv += dims[s] * dims[s];
+  return nv <= kPackedV;
+}
+
+template <typename T>
+void launch_rhs_mfma_gh(const DevOps<T>& op, const T* Hp, const T* in, const T* y, T* out, double coef, int n_traj,
+                        hipStream_t stream) {
+  const long long n_items = static_cast<long long>(n_traj) * op.n_ado;
+  if (n_items == 0) return;
+  if (!mfma_gh_supported<T>(op.d, op.n_modes, op.dims))
+    throw std::runtime_error("the H-from-global matrix-core kernel needs FP32, d in 65..80 and packed v_s <= 128");
+  if constexpr (sizeof(T) == 4) {
+    const T c = static_cast<T>(coef);
+    if (op.d % 4 == 0) launch_gh_vw<T, 4>(op, Hp, in, y, out, c, n_items, stream);
+    else launch_gh_vw<T, 1>(op, Hp, in, y, out, c, n_items, stream);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw std::runtime_error(std::string("mfma gh kernel: ") + hipGetErrorString(e));
+}
 
 template <typename T>
 bool mfma_supported(int d, int n_modes, const int* dims) {
@@ -1127,6 +1211,10 @@ template void launch_rhs_mfma_multi<float>(const InstDesc<float>*, int, int, int
 template void launch_rhs_mfma_multi<double>(const InstDesc<double>*, int, int, int, double, long long, hipStream_t,
                                             MultiShape);
 
+template bool mfma_gh_supported<float>(int, int, const int*);
+template bool mfma_gh_supported<double>(int, int, const int*);
+template void launch_rhs_mfma_gh<float>(const DevOps<float>&, const float*, const float*, const float*, float*,
+                                        double, int, hipStream_t);
 template bool mfma_static_shape<float>(const DevOps<float>&);
 template bool mfma_static_shape<double>(const DevOps<double>&);
 template bool mfma_supported<float>(int, int, const int*);

@@ -31,7 +31,8 @@ HEOM_PADE, HEOM_MATSUBARA = 0, 1
 HEOM_OP_MU, HEOM_OP_MU_PLUS, HEOM_OP_MU_MINUS = 0, 1, 2
 HEOM_RESP_DIRECT, HEOM_RESP_ADJOINT = 0, 1
 HEOM_KERNEL_AUTO, HEOM_KERNEL_GENERIC, HEOM_KERNEL_MFMA, HEOM_KERNEL_MFMA_DYN, HEOM_KERNEL_KRON = 0, 1, 2, 3, 4
-KERNELS = {"auto": 0, "generic": 1, "mfma": 2, "mfma_dyn": 3, "kron": 4}
+HEOM_KERNEL_MFMA_GH = 5
+KERNELS = {"auto": 0, "generic": 1, "mfma": 2, "mfma_dyn": 3, "kron": 4, "mfma_gh": 5}
 KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
 
 _PREC = {"fp64": HEOM_FP64, "fp32": HEOM_FP32, HEOM_FP64: HEOM_FP64, HEOM_FP32: HEOM_FP32}
@@ -759,10 +760,10 @@ def heom_model_get_kernel(model, precision):
 def heom_autotune(model, n_traj, precision="fp32", reps=2):
     """Times the kernel variants; returns (chosen name, {name: ms per RK4 step})."""
     k = C.c_int()
-    ms = np.full(HEOM_KERNEL_KRON + 1, np.nan)
+    ms = np.full(HEOM_KERNEL_MFMA_GH + 1, np.nan)
     _check(_lib.heom_autotune(model.handle, int(n_traj), _PREC[precision], int(reps), C.byref(k),
                               _ptr(ms)))
-    return KERNEL_NAMES[k.value], {KERNEL_NAMES[i]: float(ms[i]) for i in range(1, HEOM_KERNEL_KRON + 1)
+    return KERNEL_NAMES[k.value], {KERNEL_NAMES[i]: float(ms[i]) for i in range(1, HEOM_KERNEL_MFMA_GH + 1)
                                     if np.isfinite(ms[i])}
 
 

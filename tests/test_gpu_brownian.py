@@ -49,14 +49,14 @@ CASES = [("cfg1", 3), ("cfg2", 2), ("cfg3b", 2)]
 @pytest.mark.parametrize("which,depth", CASES)
 @pytest.mark.parametrize("adjoint", [False, True])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("kernel", ["generic", "mfma", "mfma_dyn", "kron"])
+@pytest.mark.parametrize("kernel", ["generic", "mfma", "mfma_dyn", "kron", "mfma_gh"])
 def test_rhs_parity_brownian(which, depth, adjoint, prec, kernel):
     params = _params(which, depth)
     o = om.build(params)
     assert np.any(np.imag(o.nu) != 0)
     m = P.heom_model_build(params)
-    if kernel == "kron" and (prec != "fp32" or which != "cfg3b"):
-        # the (S; 4, 4) kernel needs FP32 and the three-mode (4, 4, 5) shape
+    if kernel in ("kron", "mfma_gh") and (prec != "fp32" or which != "cfg3b"):
+        # both need FP32 and the three-mode (4, 4, 5) shape (d = 80)
         with pytest.raises(P.heom2dvs.HeomError):
             P.heom_model_set_kernel(m, prec, kernel)
         return

@@ -52,12 +52,20 @@ def _relerr(a, b):
 CASES = [("cfg1", None), ("cfg2", None), ("cfg2", 2), ("cfg3", 2), ("paper_scale", 2)]
 
 
-KERNELS = ["generic", "mfma", "mfma_dyn", "kron"]
+KERNELS = ["generic", "mfma", "mfma_dyn", "kron", "mfma_gh"]
 
 
 def _kron_applies(which, prec):
     # the (S; 4, 4) matrix-core kernel: FP32, three modes of (4|5, 4, 4) levels
     return prec == "fp32" and which in ("cfg3", "paper_scale")
+
+
+def _applies(kernel, which, prec):
+    if kernel == "kron":
+        return _kron_applies(which, prec)
+    if kernel == "mfma_gh":  # FP32, d = 65..80 (the three-mode 4 x 4 x 5 model)
+        return prec == "fp32" and which == "cfg3"
+    return True
 
 
 @pytest.mark.parametrize("which,depth", CASES)
@@ -68,7 +76,7 @@ def test_rhs_parity(which, depth, adjoint, prec, kernel):
     params = _params(which, depth)
     o = om.build(params)
     m = P.heom_model_build(params)
-    if kernel == "kron" and not _kron_applies(which, prec):
+    if not _applies(kernel, which, prec):
         with pytest.raises(P.heom2dvs.HeomError) as e:
             P.heom_model_set_kernel(m, prec, kernel)
         assert e.value.code == P.heom2dvs.HEOM_ERR_PARAM
@@ -118,7 +126,7 @@ def test_rhs_parity_full_depth_three_modes():
     ref = oh.rhs(o, x)
     for kernel in KERNELS:
         for prec, tol in (("fp64", 1e-12), ("fp32", 2e-6)):
-            if kernel == "kron" and prec == "fp64":
+            if kernel in ("kron", "mfma_gh") and prec == "fp64":
                 continue
             P.heom_model_set_kernel(m, prec, kernel)
             a, b = P.State(m, 2, prec), P.State(m, 2, prec)
@@ -130,9 +138,9 @@ def test_rhs_parity_full_depth_three_modes():
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_rk4_steps_parity(prec, tol, kernel):
-    params = _params("cfg3", 2) if kernel == "kron" else _params("cfg2", 3)
-    if kernel == "kron" and prec == "fp64":
-        pytest.skip("the (S; 4, 4) kernel is FP32 only")
+    params = _params("cfg3", 2) if kernel in ("kron", "mfma_gh") else _params("cfg2", 3)
+    if kernel in ("kron", "mfma_gh") and prec == "fp64":
+        pytest.skip("FP32-only kernel")
     o = om.build(params)
     m = P.heom_model_build(params)
     P.heom_model_set_kernel(m, prec, kernel)
@@ -160,7 +168,7 @@ def full_size_refs():
     return params, x, oh.rk4_step(o, x), oh.rk4_step(o, g)
 
 
-@pytest.mark.parametrize("kernel", ["mfma", "mfma_dyn", "kron"])
+@pytest.mark.parametrize("kernel", ["mfma", "mfma_dyn", "kron", "mfma_gh"])
 def test_full_size_batched_step_sampled(full_size_refs, kernel):
     """Three-mode depth-6 model, 128 trajectories (the benchmark batch) with
     either matrix-core instantiation the benchmark's autotuner may choose:
@@ -321,7 +329,7 @@ def test_autotune_picks_a_measured_kernel():
     # kernel in FP32
     for which, depth, prec, want in (("cfg2", 3, "fp32", {"generic", "mfma"}),
                                      ("cfg1", None, "fp64", {"generic", "mfma", "mfma_dyn"}),
-                                     ("cfg3", 1, "fp32", {"generic", "mfma", "kron"})):
+                                     ("cfg3", 1, "fp32", {"generic", "mfma", "kron", "mfma_gh"})):
         m = P.heom_model_build(_params(which, depth))
         P.heom_model_set_kernel(m, prec, "generic")
         best, ms = P.heom_autotune(m, 4, prec, reps=2)
@@ -594,8 +602,8 @@ def test_rhs_parity_rate_filtered_hierarchy(which, depth, cut, prec, kernel):
     assert len(o.hier) < len(om.build(_params(which, depth)).hier)
     m = P.heom_model_build(params)
     assert m.n_ado == len(o.hier)
-    if kernel == "kron" and not _kron_applies(which, prec):
-        pytest.skip("the (S; 4, 4) kernel needs FP32 and the three-mode shape")
+    if not _applies(kernel, which, prec):
+        pytest.skip("kernel not applicable to this model and precision")
     P.heom_model_set_kernel(m, prec, kernel)
     x = w.random_hierarchy(2, len(o.hier), o.d, seed=21, scale_by_depth=_depth_scale(o))
     xin = P.State(m, 2, prec)

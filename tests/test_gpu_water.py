@@ -1,8 +1,8 @@
 """GPU parity of the paper's water models (Tables I-III; reading of the tables
 in workloads.water_two_mode / water_three_mode) at reduced hierarchy depth,
 against the CPU FP64 oracle: the linear response R1 and its line shape
-(Eq. R1 and the 1D spectrum, Sec. II.C) for the two-mode model at three and
-four levels per mode and the three-mode model at three levels, and a small
+(Eq. R1 and the 1D spectrum, Sec. II.C) for both models at three and four
+levels per mode, and a small
 2D response of the two-mode model.  The input state is 200 oracle RK4 steps
 from the ground state (parity holds for any input; the oracle's dense
 stationary solve is too slow at these sizes).
@@ -37,7 +37,7 @@ def _relerr(a, b):
 MODELS = {"two": w.water_two_mode, "three": w.water_three_mode}
 
 
-@pytest.mark.parametrize("which,levels,depth", [("two", 4, 2), ("two", 3, 2), ("three", 3, 1)])
+@pytest.mark.parametrize("which,levels,depth", [("two", 4, 2), ("two", 3, 2), ("three", 3, 1), ("three", 4, 1)])
 def test_water_linear_response_parity(which, levels, depth):
     p = MODELS[which](n_levels=levels, depth=depth)
     o = om.build(p)
