@@ -14,17 +14,25 @@ spectrum against the FP64 path, the equilibration with its convergence flag, a
 short FP64 propagation leg with its own roofline, the roofline of the dominant
 kernel from HIP-event timings of its launches inside the timed region, the
 uneven multi-instance batch in each launch form, the reverse-mode gradient of
-the gradient workload's depth-6 model on a 2 x 2 grid, and the CPU oracle's
+the gradient workload's depth-6 model (one t1 / t3 sample, two t2 values), and the CPU oracle's
 rate on a bounded sample (all cores and one core).
+
+The whole run keeps to a wall-clock budget (--wall-budget, counted from the
+start of the process, imports included): the spectrum legs always run; the CPU
+baseline, the gradient and the multi-instance legs, in that order, run only if
+their usual duration still fits, and are otherwise reported as skipped.
 """
 
 from __future__ import annotations
+
+import time
+
+_T_START = time.time()
 
 import argparse
 import json
 import os
 import sys
-import time
 
 import numpy as np
 
@@ -36,15 +44,11 @@ sys.path.insert(0, ROOT)
 # scaled by the counters' readings for kernels of known size.  Keyed by the
 # kernel source hash: a changed kernel reports traffic null until re-profiled.
 PROFILED_TRAFFIC = {  # source hash -> kernel choice -> bytes per launch
-    # db1af44dac001634: profiled as 1e73106a80d7a912; the later edits add the
-    # multi-instance, single-launch and H-from-global kernels only (the device
-    # assembly of every rhs_mfma_kernel instantiation, hipcc --cuda-device-only -S,
-    # is instruction for instruction the same)
-    "db1af44dac001634": {  # FP32 at this shape: both choices run the runtime-shape kernel
-        "mfma": {"read_GB": 319.4, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
-        "mfma_dyn": {"read_GB": 319.4, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
+    "6619fa0244e5ed0b": {  # FP32 at this shape: both choices run the runtime-shape kernel
+        "mfma": {"read_GB": 328.9, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
+        "mfma_dyn": {"read_GB": 328.9, "write_GB": 32.8, "batch": 128, "precision": "fp32"},
         # the FP64 leg: 32 trajectories
-        "fp64:mfma": {"read_GB": 155.6, "write_GB": 16.4, "batch": 32, "precision": "fp64"},
+        "fp64:mfma": {"read_GB": 154.7, "write_GB": 16.4, "batch": 32, "precision": "fp64"},
     },
 }
 
@@ -203,10 +207,10 @@ def multi_instance(P, torch, precision, stream, compare=False):
 def gradient_timing(P, torch, stream):
     """Reverse-mode gradient (FP64) of a random linear functional of the
     responses of the gradient workload's model (three modes, depth 6: 5005 ADOs
-    of 80 x 80; t2 in {0, 100 fs}) on a 2 x 2 grid every 10 steps, rho held
-    fixed (200 RK4 steps from the ground state): seconds for the forward
-    responses, for the vjp (operator gradients) and for the chain to the 12
-    fitted parameters.  One t1 and one t3 sample (t1 = t3 = 0), so the cost is
+    of 80 x 80; t2 in {0, 100 fs}), rho held fixed (200 RK4 steps from the
+    ground state): seconds for the forward responses, for the vjp (operator
+    gradients) and for the chain to the 12 fitted parameters.  One t1 and one
+    t3 sample (t1 = t3 = 0), so the cost is
     the t2 propagation of both pathways and its adjoint sweep; the 64 x 64 grid
     propagates 64 trajectories per pathway through t2 instead of one."""
     import workloads as w
@@ -344,6 +348,16 @@ def spectrum_legs(P, torch, w, m, params, grid, args):
     return out
 
 
+def leg_skip_reason(elapsed_s, usual_s, budget_s):
+    """None if an optional leg of usual duration usual_s (MI355X, default
+    sizes) still fits the wall-clock budget after elapsed_s, else the reason
+    recorded in its place."""
+    if elapsed_s + usual_s <= budget_s:
+        return None
+    return (f"wall-clock budget: {elapsed_s:.0f} s elapsed, leg takes about {usual_s:.0f} s, "
+            f"budget {budget_s:.0f} s")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -375,6 +389,8 @@ def main():
                          "brownian: cfg3's modes with Brownian baths (complex rate pairs), "
                          "12 terms, depth 5 (6188 ADOs)")
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "mfma", "mfma_dyn", "kron", "mfma_gh"])
+    ap.add_argument("--wall-budget", type=float, default=570.0,
+                    help="seconds from process start within which the optional legs must finish")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path shards into independent "
@@ -473,16 +489,26 @@ def main():
         line.update(spectrum_legs(P, torch, w, m, params, grid, args))
         leg_done("spectrum")
     del s
-    if args.multi:
+
+    def fits(name, usual_s):
+        why = leg_skip_reason(time.time() - _T_START, usual_s, args.wall_budget)
+        if why is None:
+            return True
+        line[name] = {"skipped": why}
+        print(f"{name} leg skipped (budget)", file=sys.stderr, flush=True)
+        return False
+
+    if args.cpu_baseline and fits("cpu_baseline", 25.0):
+        line["cpu_baseline"] = cpu_baseline(params)
+        leg_done("cpu baseline")
+    if args.grad and fits("gradient", 55.0):
+        line["gradient"] = gradient_timing(P, torch, stream.cuda_stream)
+        leg_done("gradient")
+    if args.multi and fits("multi_instance", 25.0 if args.multi == 1 else 120.0):
         line["multi_instance"] = multi_instance(P, torch, args.precision, stream.cuda_stream,
                                                 compare=args.multi > 1)
         leg_done("multi-instance")
-    if args.grad:
-        line["gradient"] = gradient_timing(P, torch, stream.cuda_stream)
-        leg_done("gradient")
-    if args.cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(params)
-        leg_done("cpu baseline")
+    line["wall_s"] = time.time() - _T_START
     print(json.dumps(line))
 
 

@@ -28,3 +28,14 @@ def test_algorithmic_flops_count_matches_hand_count():
     m = P.heom_model_build_host(params)
     d = 80
     assert bench.algorithmic_flops_per_rhs(m) == 8 * d ** 3 + 8 * d * d * (4 + 4 + 5) + 6 * d * d
+
+
+def test_optional_legs_keep_to_the_wall_budget():
+    # an optional leg runs only while its usual duration fits what is left of
+    # the budget; otherwise the line records why it was skipped
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.leg_skip_reason(400.0, 55.0, 570.0) is None
+    assert bench.leg_skip_reason(515.0, 55.0, 570.0) is None
+    why = bench.leg_skip_reason(530.0, 55.0, 570.0)
+    assert why is not None and "530 s elapsed" in why and "budget 570 s" in why
