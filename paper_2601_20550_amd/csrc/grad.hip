@@ -130,21 +130,40 @@ __global__ __launch_bounds__(NB * 64) void gemm_grad_kernel(const double* __rest
     const double* U = u + it * 2 * dd;
     const double* Z = z + it * 2 * dd;
     __syncthreads();  // previous item's LDS reads are complete
-    for (int e = tid; e < d * d; e += NT) {
-      const int x = e / d, y = e - x * d;
-      zr[x * LDZ + y] = Z[e];
-      zi[x * LDZ + y] = Z[e + dd];
+    // z in groups of SG elements per thread, every load of a group issued
+    // before its LDS stores (a load-then-store loop pays one memory round
+    // trip per element row)
+    constexpr int SG = (NB >= 3 && NB <= 5) ? 4 * NB : 2 * NB;
+    for (int e0 = tid; e0 < d * d; e0 += SG * NT) {
+      double vr[SG], vi[SG];
+#pragma unroll
+      for (int g = 0; g < SG; ++g) {
+        const int e = e0 + g * NT;
+        const int ec = e < d * d ? e : e0;
+        vr[g] = Z[ec];
+        vi[g] = Z[ec + dd];
+      }
+#pragma unroll
+      for (int g = 0; g < SG; ++g) {
+        const int e = e0 + g * NT;
+        if (e < d * d) {
+          const int x = e / d, y = e - x * d;
+          zr[x * LDZ + y] = vr[g];
+          zi[x * LDZ + y] = vi[g];
+        }
+      }
     }
     __syncthreads();
-    // Re(f u z^T): sum over columns c of u and z
-#pragma unroll 2
+    // Re(f u z^T): sum over columns c of u and z.  The u loads are
+    // unconditional (clamped address, zero selected outside the matrix) so
+    // that they can be issued ahead of the matrix-core chain.
+#pragma unroll NB
     for (int c0 = 0; c0 < DP; c0 += 4) {
       const int c = c0 + lk;
-      double ur = 0.0, ui = 0.0;
-      if (ia < d && c < d) {
-        ur = U[ia * d + c];
-        ui = U[ia * d + c + dd];
-      }
+      const bool in = ia < d && c < d;
+      const int off = in ? ia * d + c : 0;
+      const double ur0 = U[off], ui0 = U[off + dd];
+      const double ur = in ? ur0 : 0.0, ui = in ? ui0 : 0.0;
       const double ar = f_re * ur - f_im * ui, ai = -(f_re * ui + f_im * ur);
 #pragma unroll
       for (int tj = 0; tj < NB; ++tj) {
@@ -154,14 +173,13 @@ __global__ __launch_bounds__(NB * 64) void gemm_grad_kernel(const double* __rest
       }
     }
     // Re(z^T f u): sum over rows x of z and u
-#pragma unroll 2
+#pragma unroll NB
     for (int x0 = 0; x0 < DP; x0 += 4) {
       const int x = x0 + lk;
-      double ur = 0.0, ui = 0.0;
-      if (x < d && ia < d) {
-        ur = U[x * d + ia];
-        ui = U[x * d + ia + dd];
-      }
+      const bool in = x < d && ia < d;
+      const int off = in ? x * d + ia : 0;
+      const double ur0 = U[off], ui0 = U[off + dd];
+      const double ur = in ? ur0 : 0.0, ui = in ? ui0 : 0.0;
       const double br = f_re * ur - f_im * ui, bi = -(f_re * ui + f_im * ur);
 #pragma unroll
       for (int ti = 0; ti < NB; ++ti) {
@@ -263,10 +281,26 @@ __global__ __launch_bounds__(NBT) void nb_grad_kernel(GradOps g, int s, const do
     const double* U = u + it * 2 * dd;
     const double* Zt = z + traj * g.n_ado * 2 * dd;
     __syncthreads();
-    for (int e = tid; e < d * d; e += NBT) {
-      const int x = e / d, yy = e - x * d;
-      sur[x * LD + yy] = U[e];
-      sui[x * LD + yy] = U[e + dd];
+    // u in groups of 8 elements per thread, loads before LDS stores (as in
+    // gemm_grad_kernel)
+    for (int e0 = tid; e0 < d * d; e0 += 8 * NBT) {
+      double vr[8], vi[8];
+#pragma unroll
+      for (int g8 = 0; g8 < 8; ++g8) {
+        const int e = e0 + g8 * NBT;
+        const int ec = e < d * d ? e : e0;
+        vr[g8] = U[ec];
+        vi[g8] = U[ec + dd];
+      }
+#pragma unroll
+      for (int g8 = 0; g8 < 8; ++g8) {
+        const int e = e0 + g8 * NBT;
+        if (e < d * d) {
+          const int x = e / d, yy = e - x * d;
+          sur[x * LD + yy] = vr[g8];
+          sui[x * LD + yy] = vi[g8];
+        }
+      }
     }
     const int q0 = g.nb_ptr[n * g.n_modes + s];
     const int nq = min(g.nb_ptr[n * g.n_modes + s + 1] - q0, MAXQ);
